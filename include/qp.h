@@ -1,0 +1,276 @@
+/*
+ * qp.h -- C ABI of the MI355X all-pairs posterior engine.
+ *
+ * The engine computes stage I of QuickProbs 2 (Gudys & Deorowicz, "QuickProbs 2:
+ * Towards rapid construction of high-quality alignments of large protein
+ * families"): for every pair of sequences of a family, the posterior
+ * probability that residue x_i is aligned with residue y_j, from a pair hidden
+ * Markov model and from a partition function over alignments (Methods, opening
+ * paragraph), combined into one matrix, kept sparse by a threshold (Methods,
+ * "Selective consistency", footnote on the sparsity coefficient; "Other
+ * algorithmic improvements", memory as the limit on family size), together
+ * with the maximum-expected-accuracy score that stage II turns into a
+ * distance (Methods, opening paragraph).
+ *
+ * Model (the paper names the models but does not restate them; the readings
+ * are fixed here):
+ *   alignment     monotone sequence of match columns M(i,j), x-gap columns and
+ *                 y-gap columns using every residue once; a gap column of x is
+ *                 never adjacent to a gap column of y; begin and end behave as
+ *                 match columns.
+ *   pair-HMM      match emission odds e_ab = p_ab / (qx_a qy_b) from the joint
+ *                 p (qx, qy its marginals); G gap classes, M->gap_k delta_k,
+ *                 gap_k->gap_k eps_k, gap_k->M 1-eps_k, M->M 1-2*sum(delta).
+ *   partition fn  weight exp(score/T), score = sum of s_ab over matches plus
+ *                 pf_gap_open + (L-1)*pf_gap_extend for every gap run of
+ *                 length L (terminal runs included).
+ *   posterior     P = w_hmm * P_hmm + (1 - w_hmm) * P_pf.
+ *   sparse form   entries with P >= thresh, CSR per pair, rows = residues of
+ *                 the first sequence, columns ascending.
+ *   distance      A(i,j) = max(A(i-1,j-1) + P(i,j), A(i-1,j), A(i,j-1)) on the
+ *                 dense P; EA = A(m,n) / min(m,n); dist = 1 - EA.
+ *
+ * Pairs.  In all-pairs mode the pairs of an n-sequence family are (i<j) in
+ * row-major order, p = i*n - i*(i+1)/2 + (j-i-1); P(j,i) is P(i,j) transposed
+ * (the model is symmetric in x and y).  Explicit pair lists are also accepted.
+ *
+ * Errors.  Every call returns qp_status; nothing throws across the ABI.  On
+ * error, output pointers are set to NULL, nothing is leaked, and
+ * qp_last_error() returns a message (thread-local, valid until the next call
+ * on that thread).
+ *
+ * Threads.  Calls from different host threads are safe; calls that share a
+ * plan or a server must be serialised by the caller except where stated.
+ */
+#ifndef QP_H
+#define QP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QP_OK = 0,
+    QP_EINVAL = -1,      /* invalid argument                                  */
+    QP_ENOMEM = -2,      /* host or device memory could not be obtained       */
+    QP_EDEVICE = -3,     /* HIP runtime error or no usable gfx950 device      */
+    QP_EBUSY = -4,       /* server: result not ready (non-blocking wait)      */
+    QP_ETIMEDOUT = -5,   /* server: wait timed out                            */
+    QP_ECANCELED = -6,   /* server: request cancelled or server shut down     */
+    QP_ENOSPC = -7       /* output capacity exceeded (device-resident calls)  */
+} qp_status;
+
+enum { QP_ALPHA = 20, QP_MAX_GAP_CLASSES = 2 };
+
+/* arithmetic of the dynamic programmes */
+enum {
+    QP_FP32_SCALED = 0,  /* FP32 values, power-of-two scale per lane strip    */
+    QP_FP64 = 1          /* FP64 values, same scaling                          */
+};
+
+/*
+ * Model parameters (raw; the library derives its tables on the device).
+ * Residue codes are 0..19 in the order "ARNDCQEGHILKMFPSTWYV".
+ * Validation (QP_EINVAL): joint entries in (0,1), summing to 1 within 1e-9 and
+ * symmetric within 1e-12; 1 <= n_gap_classes <= 2; delta_k in (0, 0.5),
+ * eps_k in [0, 1), 1 - 2*sum(delta) > 0; score symmetric within 1e-12 and
+ * finite; temperature > 0; pf gap scores finite; w_hmm in [0,1];
+ * precision one of the enum above.
+ */
+typedef struct {
+    double joint[QP_ALPHA * QP_ALPHA];   /* p_ab, row = residue of x         */
+    int32_t n_gap_classes;               /* G                                */
+    double gap_open[QP_MAX_GAP_CLASSES]; /* delta_k                          */
+    double gap_extend[QP_MAX_GAP_CLASSES]; /* eps_k                          */
+    double score[QP_ALPHA * QP_ALPHA];   /* s_ab                             */
+    double pf_gap_open;                  /* score of the first gap residue   */
+    double pf_gap_extend;                /* score of each further gap residue*/
+    double temperature;                  /* T                                */
+    double w_hmm;                        /* weight of the HMM posterior      */
+    int32_t precision;                   /* QP_FP32_SCALED or QP_FP64        */
+} qp_params;
+
+/*
+ * Host-resident result (library-owned; release with qp_result_free).
+ * Pair p covers rows row_off[p] .. row_off[p+1]-1 of row_ptr (m_p + 1 local
+ * row pointers starting at 0) and entries nnz_off[p] .. nnz_off[p+1]-1 of
+ * col/val.  col is the 0-based residue index in the second sequence.
+ */
+typedef struct {
+    int32_t n_seqs;
+    int64_t n_pairs;
+    int64_t total_rows;     /* row_off[n_pairs]                               */
+    int64_t nnz;            /* nnz_off[n_pairs]                               */
+    int32_t* pair_i;        /* [n_pairs] first sequence (rows)                */
+    int32_t* pair_j;        /* [n_pairs] second sequence (columns)            */
+    int64_t* row_off;       /* [n_pairs + 1]                                  */
+    int32_t* row_ptr;       /* [total_rows]                                   */
+    int64_t* nnz_off;       /* [n_pairs + 1]                                  */
+    int32_t* col;           /* [nnz]                                          */
+    float* val;             /* [nnz] combined posterior                       */
+    double* dist;           /* [n_pairs] 1 - EA                               */
+    double* log_z;          /* [2 * n_pairs] log Z_hmm, log Z_pf per pair     */
+    double device_ms;       /* device time of the posterior pipeline          */
+} qp_result;
+
+/* Library version, (major << 16) | minor. */
+int32_t qp_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* qp_last_error(void);
+
+/* Fill *p with the defaults used by the benchmark workloads: no joint or
+ * score (zeros -- the caller must provide them), G = 2 with delta =
+ * (0.02, 0.005), eps = (0.5, 0.9), PF gaps -12 / -1, T = 5, w_hmm = 0.5,
+ * QP_FP32_SCALED.  Never fails. */
+void qp_params_default(qp_params* p);
+
+/* Validate parameters without touching the device.  QP_OK or QP_EINVAL. */
+qp_status qp_params_check(const qp_params* p);
+
+/*
+ * All-pairs posteriors of one family (the stage-I computation, Methods,
+ * opening paragraph).
+ *   seqs[n]   host pointers to residue codes (0..19); borrowed for the call
+ *   lens[n]   sequence lengths, each >= 1
+ *   n         number of sequences (n < 2 gives a result with zero pairs)
+ *   params    model, see qp_params
+ *   thresh    sparsity threshold in (0, 1]
+ *   out       receives a library-owned result on QP_OK, NULL otherwise
+ * Runs on the current HIP device on an internal stream and blocks until the
+ * result is on the host.
+ */
+qp_status qp_posteriors(const uint8_t* const* seqs, const int32_t* lens, int32_t n,
+                        const qp_params* params, float thresh, qp_result** out);
+
+/* Same for an explicit list of pairs (pair_i[k], pair_j[k]), 0 <= index < n,
+ * pair_i[k] != pair_j[k]; rows are residues of seqs[pair_i[k]].  Result pair
+ * k is list entry k. */
+qp_status qp_posteriors_pairs(const uint8_t* const* seqs, const int32_t* lens, int32_t n,
+                              const int32_t* pair_i, const int32_t* pair_j, int64_t n_pairs,
+                              const qp_params* params, float thresh, qp_result** out);
+
+/* Release a result (NULL-safe). */
+void qp_result_free(qp_result* r);
+
+/* ------------------------------------------------------------------------
+ * Device-resident form.  A plan fixes the family shape (lengths, pair list,
+ * parameters, threshold), owns the device workspace and output buffers and
+ * a captured HIP graph of the whole pipeline.  Inputs are device pointers
+ * the caller owns (for instance torch tensors); the stream is the caller's.
+ * ---------------------------------------------------------------------- */
+typedef struct qp_plan qp_plan;
+
+/* Device pointers into plan-owned outputs, valid until the next run or
+ * qp_plan_destroy.  Layout as qp_result. */
+typedef struct {
+    int64_t n_pairs;
+    int64_t total_rows;
+    int64_t nnz;            /* filled by qp_plan_sync                         */
+    const int32_t* pair_i;
+    const int32_t* pair_j;
+    const int64_t* row_off;
+    const int32_t* row_ptr;
+    const int64_t* nnz_off;
+    const int32_t* col;
+    const float* val;
+    const double* dist;
+    const double* log_z;
+} qp_device_result;
+
+/*
+ * Create a plan on the current device.
+ *   lens[n]          host copy of the sequence lengths
+ *   pair_i, pair_j   NULL for all pairs, else a host pair list of n_pairs
+ *   nnz_capacity     initial capacity of the sparse output (entries); 0 lets
+ *                    the library estimate it; a run that overflows reports
+ *                    QP_ENOSPC from qp_plan_sync and grows the plan so that
+ *                    the next run fits
+ * Allocates device memory (QP_ENOMEM if it cannot).
+ */
+qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                         int64_t n_pairs, const qp_params* params, float thresh, int64_t nnz_capacity,
+                         qp_plan** plan);
+
+/* Enqueue the whole pipeline on `stream` (a hipStream_t, NULL = legacy
+ * default).  d_seqs: residue codes of all sequences concatenated; d_seq_off:
+ * int64 start offset of each sequence in d_seqs ([n]); both device pointers,
+ * read during the run.  Asynchronous. */
+qp_status qp_plan_run(qp_plan* plan, const uint8_t* d_seqs, const int64_t* d_seq_off, void* stream);
+
+/* Wait for the last run on its stream, check for output overflow and fill
+ * *res (may be NULL).  QP_ENOSPC if the sparse output did not fit (the plan
+ * is grown; run again). */
+qp_status qp_plan_sync(qp_plan* plan, qp_device_result* res);
+
+/* Copy the last run's outputs to a library-owned host result. */
+qp_status qp_plan_download(qp_plan* plan, qp_result** out);
+
+/* Average device time (ms) of the posterior kernel and of the whole
+ * pipeline over the runs since the last reset, from HIP events recorded on
+ * the run stream; *n_runs receives the number of runs averaged. */
+qp_status qp_plan_timing(qp_plan* plan, double* kernel_ms, double* pipeline_ms, int64_t* n_runs, int32_t reset);
+
+/* Use (1) or stop using (0) the captured HIP graph for subsequent runs
+ * (default 1). */
+qp_status qp_plan_set_graph(qp_plan* plan, int32_t use_graph);
+
+/* Device bytes held by the plan. */
+int64_t qp_plan_device_bytes(const qp_plan* plan);
+
+void qp_plan_destroy(qp_plan* plan);
+
+/* ------------------------------------------------------------------------
+ * Serving: families arrive over time; each is admitted when the free device
+ * memory budget covers its workspace and outputs and a slot is free; admitted
+ * families run concurrently on a pool of streams (continuous batching), and
+ * each result is identical to the result of the same family run alone.
+ * ---------------------------------------------------------------------- */
+typedef struct qp_server qp_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;   /* device memory the server may hold (> 0)  */
+    int32_t max_slots;          /* families in flight at once (1..64)       */
+    int32_t n_streams;          /* streams in the pool (1..16)              */
+} qp_server_config;
+
+typedef struct {
+    double submit_s;            /* host clock at submit (seconds)           */
+    double admit_s;             /* host clock when admitted                 */
+    double done_s;              /* host clock when the result was ready     */
+    int64_t cells;              /* sum of m*n over the family's pairs       */
+} qp_request_times;
+
+/* Create a server on the current device (starts one scheduler thread). */
+qp_status qp_server_create(const qp_server_config* cfg, qp_server** s);
+
+/* Submit a family; inputs are copied.  QP_ENOMEM if the family could never
+ * fit in the budget.  Thread-safe. */
+qp_status qp_server_submit(qp_server* s, const uint8_t* const* seqs, const int32_t* lens, int32_t n,
+                           const qp_params* params, float thresh, uint64_t* ticket);
+
+/* Wait for a ticket: timeout_ms < 0 blocks, 0 polls (QP_EBUSY if not
+ * ready).  On QP_OK the result is handed over (free with qp_result_free) and
+ * the ticket is retired.  Thread-safe. */
+qp_status qp_server_wait(qp_server* s, uint64_t ticket, int32_t timeout_ms, qp_result** out,
+                         qp_request_times* times);
+
+/* Cancel a queued (not yet admitted) request.  QP_EBUSY if already running. */
+qp_status qp_server_cancel(qp_server* s, uint64_t ticket);
+
+/* Counters: families queued, in flight, finished; device bytes in use. */
+qp_status qp_server_stats(qp_server* s, int64_t* queued, int64_t* in_flight, int64_t* finished,
+                          int64_t* bytes_in_use);
+
+/* Stop the scheduler; waits for in-flight work; pending requests are
+ * cancelled. */
+qp_status qp_server_destroy(qp_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QP_H */

@@ -1,0 +1,297 @@
+"""ctypes binding of ``libqp.so`` (the C ABI declared in ``include/qp.h``).
+
+Argument marshalling only: every step of the posterior computation runs in
+the library's gfx950 kernels.  Functions keep the C names.  If the library is
+missing, importing this module raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqp.so")
+
+QP_OK, QP_EINVAL, QP_ENOMEM, QP_EDEVICE, QP_EBUSY, QP_ETIMEDOUT, QP_ECANCELED, QP_ENOSPC = 0, -1, -2, -3, -4, -5, -6, -7
+QP_FP32_SCALED, QP_FP64 = 0, 1
+STATUS_NAMES = {0: "QP_OK", -1: "QP_EINVAL", -2: "QP_ENOMEM", -3: "QP_EDEVICE", -4: "QP_EBUSY",
+                -5: "QP_ETIMEDOUT", -6: "QP_ECANCELED", -7: "QP_ENOSPC"}
+
+
+class QpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class qp_params(ctypes.Structure):
+    _fields_ = [("joint", ctypes.c_double * 400), ("n_gap_classes", ctypes.c_int32),
+                ("gap_open", ctypes.c_double * 2), ("gap_extend", ctypes.c_double * 2),
+                ("score", ctypes.c_double * 400), ("pf_gap_open", ctypes.c_double),
+                ("pf_gap_extend", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("w_hmm", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class qp_result(ctypes.Structure):
+    _fields_ = [("n_seqs", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("total_rows", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("pair_i", ctypes.POINTER(ctypes.c_int32)),
+                ("pair_j", ctypes.POINTER(ctypes.c_int32)), ("row_off", ctypes.POINTER(ctypes.c_int64)),
+                ("row_ptr", ctypes.POINTER(ctypes.c_int32)), ("nnz_off", ctypes.POINTER(ctypes.c_int64)),
+                ("col", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_float)),
+                ("dist", ctypes.POINTER(ctypes.c_double)), ("log_z", ctypes.POINTER(ctypes.c_double)),
+                ("device_ms", ctypes.c_double)]
+
+
+class qp_device_result(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("total_rows", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("pair_i", ctypes.c_void_p), ("pair_j", ctypes.c_void_p), ("row_off", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("nnz_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("dist", ctypes.c_void_p), ("log_z", ctypes.c_void_p)]
+
+
+class qp_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("n_streams", ctypes.c_int32)]
+
+
+class qp_request_times(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("cells", ctypes.c_int64)]
+
+
+# every function the header declares: name -> (restype, argtypes)
+_P = ctypes.POINTER
+_u8pp = _P(_P(ctypes.c_uint8))
+SIGNATURES = {
+    "qp_version": (ctypes.c_int32, []),
+    "qp_last_error": (ctypes.c_char_p, []),
+    "qp_params_default": (None, [_P(qp_params)]),
+    "qp_params_check": (ctypes.c_int, [_P(qp_params)]),
+    "qp_posteriors": (ctypes.c_int, [_u8pp, _P(ctypes.c_int32), ctypes.c_int32, _P(qp_params), ctypes.c_float,
+                                     _P(_P(qp_result))]),
+    "qp_posteriors_pairs": (ctypes.c_int, [_u8pp, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32),
+                                           _P(ctypes.c_int32), ctypes.c_int64, _P(qp_params), ctypes.c_float,
+                                           _P(_P(qp_result))]),
+    "qp_result_free": (None, [_P(qp_result)]),
+    "qp_plan_create": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                      ctypes.c_int64, _P(qp_params), ctypes.c_float, ctypes.c_int64,
+                                      _P(ctypes.c_void_p)]),
+    "qp_plan_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "qp_plan_sync": (ctypes.c_int, [ctypes.c_void_p, _P(qp_device_result)]),
+    "qp_plan_download": (ctypes.c_int, [ctypes.c_void_p, _P(_P(qp_result))]),
+    "qp_plan_timing": (ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), _P(ctypes.c_double),
+                                      _P(ctypes.c_int64), ctypes.c_int32]),
+    "qp_plan_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "qp_plan_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "qp_plan_destroy": (None, [ctypes.c_void_p]),
+    "qp_server_create": (ctypes.c_int, [_P(qp_server_config), _P(ctypes.c_void_p)]),
+    "qp_server_submit": (ctypes.c_int, [ctypes.c_void_p, _u8pp, _P(ctypes.c_int32), ctypes.c_int32, _P(qp_params),
+                                        ctypes.c_float, _P(ctypes.c_uint64)]),
+    "qp_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, _P(_P(qp_result)),
+                                      _P(qp_request_times)]),
+    "qp_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "qp_server_stats": (ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int64),
+                                       _P(ctypes.c_int64), _P(ctypes.c_int64)]),
+    "qp_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqp.so is not built (%s); run __graft_entry__.build() -- there is no CPU fallback"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != QP_OK:
+        raise QpError(st, lib.qp_last_error().decode(errors="replace"))
+
+
+def qp_version() -> int:
+    return int(lib.qp_version())
+
+
+def qp_last_error() -> str:
+    return lib.qp_last_error().decode(errors="replace")
+
+
+def make_params(mp, precision: int = QP_FP32_SCALED) -> qp_params:
+    """qp_params from a ``workload.ModelParams``."""
+    p = qp_params()
+    lib.qp_params_default(ctypes.byref(p))
+    p.joint[:] = [float(v) for v in np.asarray(mp.joint, dtype=np.float64).reshape(400)]
+    p.score[:] = [float(v) for v in np.asarray(mp.score, dtype=np.float64).reshape(400)]
+    G = len(mp.gap_open)
+    p.n_gap_classes = G
+    for k in range(2):
+        p.gap_open[k] = float(mp.gap_open[k]) if k < G else 0.0
+        p.gap_extend[k] = float(mp.gap_extend[k]) if k < G else 0.0
+    p.pf_gap_open = float(mp.pf_gap_open)
+    p.pf_gap_extend = float(mp.pf_gap_extend)
+    p.temperature = float(mp.temperature)
+    p.w_hmm = float(mp.w_hmm)
+    p.precision = int(precision)
+    return p
+
+
+def qp_params_check(p: qp_params) -> int:
+    return int(lib.qp_params_check(ctypes.byref(p)))
+
+
+def _seq_array(seqs: Sequence[np.ndarray]):
+    keep = [np.ascontiguousarray(s, dtype=np.uint8) for s in seqs]
+    arr = (_P(ctypes.c_uint8) * max(1, len(keep)))()
+    for i, s in enumerate(keep):
+        arr[i] = s.ctypes.data_as(_P(ctypes.c_uint8))
+    lens = np.asarray([len(s) for s in keep], dtype=np.int32)
+    return keep, arr, lens
+
+
+def _np(ptr, count, dtype):
+    if count <= 0:
+        return np.zeros(0, dtype=dtype)
+    return np.ctypeslib.as_array(ptr, shape=(int(count),)).astype(dtype, copy=True)
+
+
+def result_to_dict(r: qp_result) -> Dict[str, np.ndarray]:
+    P, rows, nnz = r.n_pairs, r.total_rows, r.nnz
+    return dict(n_seqs=int(r.n_seqs), n_pairs=int(P), nnz=int(nnz), device_ms=float(r.device_ms),
+                pair_i=_np(r.pair_i, P, np.int32), pair_j=_np(r.pair_j, P, np.int32),
+                row_off=_np(r.row_off, P + 1, np.int64), row_ptr=_np(r.row_ptr, rows, np.int32),
+                nnz_off=_np(r.nnz_off, P + 1, np.int64), col=_np(r.col, nnz, np.int32),
+                val=_np(r.val, nnz, np.float32), dist=_np(r.dist, P, np.float64),
+                log_z=_np(r.log_z, 2 * P, np.float64))
+
+
+def qp_posteriors(seqs: Sequence[np.ndarray], params: qp_params, thresh: float) -> Dict[str, np.ndarray]:
+    """All-pairs posteriors of one family (blocking)."""
+    keep, arr, lens = _seq_array(seqs)
+    out = _P(qp_result)()
+    st = lib.qp_posteriors(arr, lens.ctypes.data_as(_P(ctypes.c_int32)), len(keep), ctypes.byref(params),
+                           ctypes.c_float(thresh), ctypes.byref(out))
+    _check(st)
+    try:
+        return result_to_dict(out.contents)
+    finally:
+        lib.qp_result_free(out)
+
+
+def qp_posteriors_pairs(seqs: Sequence[np.ndarray], pair_i, pair_j, params: qp_params,
+                        thresh: float) -> Dict[str, np.ndarray]:
+    """Posteriors of an explicit pair list (blocking)."""
+    keep, arr, lens = _seq_array(seqs)
+    pi = np.ascontiguousarray(pair_i, dtype=np.int32)
+    pj = np.ascontiguousarray(pair_j, dtype=np.int32)
+    out = _P(qp_result)()
+    st = lib.qp_posteriors_pairs(arr, lens.ctypes.data_as(_P(ctypes.c_int32)), len(keep),
+                                 pi.ctypes.data_as(_P(ctypes.c_int32)), pj.ctypes.data_as(_P(ctypes.c_int32)),
+                                 len(pi), ctypes.byref(params), ctypes.c_float(thresh), ctypes.byref(out))
+    _check(st)
+    try:
+        return result_to_dict(out.contents)
+    finally:
+        lib.qp_result_free(out)
+
+
+def pair_csr(res: Dict[str, np.ndarray], p: int):
+    """(row_ptr, col, val) of pair p from a result dict."""
+    rp = res["row_ptr"][res["row_off"][p]:res["row_off"][p + 1]]
+    a, b = res["nnz_off"][p], res["nnz_off"][p + 1]
+    return rp, res["col"][a:b], res["val"][a:b]
+
+
+def pair_dense(res: Dict[str, np.ndarray], p: int, n_cols: int) -> np.ndarray:
+    rp, c, v = pair_csr(res, p)
+    m = len(rp) - 1
+    d = np.zeros((m, n_cols), dtype=np.float64)
+    for i in range(m):
+        d[i, c[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    return d
+
+
+class Plan:
+    """Device-resident plan (qp_plan_*): inputs are torch tensors on the GPU,
+    the stream is torch's; outputs stay on the device until downloaded."""
+
+    def __init__(self, lens: Sequence[int], params: qp_params, thresh: float, pair_i=None, pair_j=None,
+                 nnz_capacity: int = 0):
+        self._lens = np.ascontiguousarray(lens, dtype=np.int32)
+        self.handle = ctypes.c_void_p()
+        if pair_i is None:
+            pi = pj = None
+            npairs = 0
+        else:
+            self._pi = np.ascontiguousarray(pair_i, dtype=np.int32)
+            self._pj = np.ascontiguousarray(pair_j, dtype=np.int32)
+            pi = self._pi.ctypes.data_as(_P(ctypes.c_int32))
+            pj = self._pj.ctypes.data_as(_P(ctypes.c_int32))
+            npairs = len(self._pi)
+        st = lib.qp_plan_create(self._lens.ctypes.data_as(_P(ctypes.c_int32)), len(self._lens), pi, pj, npairs,
+                                ctypes.byref(params), ctypes.c_float(thresh), int(nnz_capacity),
+                                ctypes.byref(self.handle))
+        _check(st)
+
+    def run(self, d_seqs_ptr: int, d_off_ptr: int, stream_ptr: int):
+        _check(lib.qp_plan_run(self.handle, ctypes.c_void_p(d_seqs_ptr), ctypes.c_void_p(d_off_ptr),
+                               ctypes.c_void_p(stream_ptr)))
+
+    def sync(self) -> qp_device_result:
+        r = qp_device_result()
+        _check(lib.qp_plan_sync(self.handle, ctypes.byref(r)))
+        return r
+
+    def sync_status(self) -> int:
+        r = qp_device_result()
+        return int(lib.qp_plan_sync(self.handle, ctypes.byref(r)))
+
+    def download(self) -> Dict[str, np.ndarray]:
+        out = _P(qp_result)()
+        _check(lib.qp_plan_download(self.handle, ctypes.byref(out)))
+        try:
+            return result_to_dict(out.contents)
+        finally:
+            lib.qp_result_free(out)
+
+    def timing(self, reset: bool = False):
+        k, p, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib.qp_plan_timing(self.handle, ctypes.byref(k), ctypes.byref(p), ctypes.byref(n), int(reset)))
+        return k.value, p.value, n.value
+
+    def set_graph(self, on: bool):
+        _check(lib.qp_plan_set_graph(self.handle, int(on)))
+
+    def device_bytes(self) -> int:
+        return int(lib.qp_plan_device_bytes(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib.qp_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_inputs(seqs: Sequence[np.ndarray], device: str = "cuda:0"):
+    """Concatenate a family into torch device tensors (codes, int64 offsets)."""
+    import torch
+    lens = np.asarray([len(s) for s in seqs], dtype=np.int64)
+    off = np.zeros(len(seqs), dtype=np.int64)
+    if len(seqs) > 1:
+        off[1:] = np.cumsum(lens)[:-1]
+    cat = np.concatenate([np.asarray(s, dtype=np.uint8) for s in seqs]) if len(seqs) else np.zeros(1, np.uint8)
+    return torch.from_numpy(cat).to(device), torch.from_numpy(off).to(device)

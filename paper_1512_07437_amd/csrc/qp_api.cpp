@@ -1,0 +1,839 @@
+// C ABI of the all-pairs posterior engine: validation, plans (device
+// workspace, longest-first schedule, captured HIP graph, timing), the
+// blocking host entry points and result transfer.  See include/qp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qp.h"
+#include "qp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+qp_status fail(qp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess) return fail(QP_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+constexpr int kNumEventSets = 8;
+
+// QP_TRACE=1 prints each host step of a call to stderr
+bool trace_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("QP_TRACE");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
+void trace(const char* fmt, ...) {
+    if (!trace_on()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[qp] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    std::fflush(stderr);
+    va_end(ap);
+}
+
+bool is_sym(const double* a, double tol) {
+    for (int i = 0; i < QP_ALPHA; ++i)
+        for (int j = i + 1; j < QP_ALPHA; ++j)
+            if (std::fabs(a[i * QP_ALPHA + j] - a[j * QP_ALPHA + i]) > tol) return false;
+    return true;
+}
+
+// check that the current device is a gfx950 GPU
+qp_status check_device(int* dev_out, int* n_cu) {
+    int dev = 0, count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(QP_EDEVICE, "no HIP device available");
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(QP_EDEVICE, "device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
+    *dev_out = dev;
+    if (n_cu) *n_cu = prop.multiProcessorCount;
+    return QP_OK;
+}
+
+int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+}  // namespace
+
+// ----------------------------------------------------------------- plan
+struct qp_plan {
+    int device = 0;
+    int32_t n = 0;
+    int64_t P = 0;
+    bool all_pairs = true;
+    std::vector<int32_t> lens;
+    std::vector<int32_t> list_i, list_j;
+    qp_params params{};
+    float thresh = 0.f;
+    int fp64 = 0;
+    int rmax = 1, nb_max = 1, mmax = 1, nmax = 1, cap = 1;
+    int grid = 1;
+    int64_t total_rows = 0;
+    int64_t pool_cap = 0;
+    qp::PairArgs args{};
+    // device memory (one allocation each; freed in destroy)
+    std::vector<void*> allocs;
+    int64_t device_bytes = 0;
+    qp::DevParams* d_params = nullptr;
+    void* d_tab = nullptr;
+    qp::DevConsts* d_consts = nullptr;
+    int32_t* d_lens = nullptr;
+    int32_t* d_list_i = nullptr;
+    int32_t* d_list_j = nullptr;
+    int32_t* d_pi = nullptr;
+    int32_t* d_pj = nullptr;
+    int64_t* d_rowoff = nullptr;
+    int32_t* d_key = nullptr;
+    int* d_ints = nullptr;   // queue head, flags, hist, bin fill, pool head (as 2 ints)
+    int n_ints = 0;
+    int* d_bin_start = nullptr;
+    int32_t* d_queue = nullptr;
+    int32_t* d_rowptr = nullptr;
+    int64_t* d_nnz = nullptr;
+    int64_t* d_base = nullptr;
+    int32_t* d_pool_col = nullptr;
+    float* d_pool_val = nullptr;
+    int32_t* d_col = nullptr;
+    float* d_val = nullptr;
+    double* d_dist = nullptr;
+    double* d_logz = nullptr;
+    int64_t* d_scan_tmp = nullptr;
+    char* d_scratch = nullptr;
+    // graph and timing
+    bool use_graph = true;
+    bool graph_broken = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec[kNumEventSets] = {};
+    const void* cap_seqs = nullptr;
+    const void* cap_off = nullptr;
+    hipEvent_t ev[kNumEventSets][4] = {};
+    bool ev_pending[kNumEventSets] = {};
+    int run_idx = 0;
+    double sum_kernel_ms = 0.0, sum_pipe_ms = 0.0;
+    int64_t n_timed = 0;
+    hipStream_t last_stream = nullptr;
+    bool ran = false;
+    int64_t last_nnz = 0;
+};
+
+namespace {
+
+template <typename T>
+qp_status dalloc(qp_plan* pl, T** out, int64_t count) {
+    void* p = nullptr;
+    const int64_t bytes = std::max<int64_t>(count, 1) * (int64_t)sizeof(T);
+    hipError_t e = hipMalloc(&p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QP_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)bytes, hipGetErrorString(e));
+    }
+    pl->allocs.push_back(p);
+    pl->device_bytes += bytes;
+    *out = static_cast<T*>(p);
+    return QP_OK;
+}
+
+void plan_free_device(qp_plan* pl) {
+    for (int g = 0; g < kNumEventSets; ++g) {
+        if (pl->exec[g]) hipGraphExecDestroy(pl->exec[g]);
+        pl->exec[g] = nullptr;
+    }
+    for (void* p : pl->allocs) hipFree(p);
+    pl->allocs.clear();
+    pl->device_bytes = 0;
+}
+
+qp_status validate_lens(const int32_t* lens, int32_t n) {
+    if (n < 0) return fail(QP_EINVAL, "n = %d < 0", n);
+    if (n > 0 && !lens) return fail(QP_EINVAL, "lens is NULL");
+    for (int32_t i = 0; i < n; ++i)
+        if (lens[i] < 1) return fail(QP_EINVAL, "lens[%d] = %d < 1 (empty sequences are not allowed)", i, lens[i]);
+    return QP_OK;
+}
+
+// sizes of one per-wave scratch slot
+void size_slot(qp_plan* pl) {
+    const int64_t v2 = pl->fp64 ? 16 : 8;
+    const int64_t steps = (int64_t)pl->nmax + qp::kWave - 1;
+    pl->args.spill_band_stride = steps * qp::kWave * pl->rmax;
+    pl->args.exps_band_stride = steps * qp::kWave;
+    pl->args.bnd_stride = pl->nmax + 2;
+    int64_t off = align256(pl->nb_max * pl->args.spill_band_stride * v2);
+    pl->args.off_exps = off;
+    off += align256(pl->nb_max * pl->args.exps_band_stride * 8);
+    pl->args.off_fb = off;
+    off += align256(2 * pl->args.bnd_stride * (int64_t)qp::fwd_bnd_bytes(pl->fp64));
+    pl->args.off_bb = off;
+    off += align256(2 * pl->args.bnd_stride * (int64_t)qp::bwd_bnd_bytes(pl->fp64));
+    pl->args.off_stage_col = off;
+    off += align256((int64_t)pl->mmax * pl->cap * 4);
+    pl->args.off_stage_val = off;
+    off += align256((int64_t)pl->mmax * pl->cap * 4);
+    pl->args.slot_bytes = off;
+}
+
+}  // namespace
+
+// allocation of all plan buffers (needs pool_cap and grid)
+static qp_status plan_alloc_all(qp_plan* pl) {
+    const int64_t P = pl->P;
+    qp_status st;
+#define ALLOC(ptr, cnt) \
+    if ((st = dalloc(pl, &(ptr), (cnt))) != QP_OK) return st
+    ALLOC(pl->d_params, 1);
+    {
+        char* t = nullptr;
+        ALLOC(t, (int64_t)qp::kTabRows * qp::kTabW * (pl->fp64 ? 16 : 8));
+        pl->d_tab = t;
+    }
+    ALLOC(pl->d_consts, 1);
+    ALLOC(pl->d_lens, pl->n);
+    if (!pl->all_pairs) {
+        ALLOC(pl->d_list_i, P);
+        ALLOC(pl->d_list_j, P);
+    }
+    ALLOC(pl->d_pi, P);
+    ALLOC(pl->d_pj, P);
+    ALLOC(pl->d_rowoff, P + 1);
+    ALLOC(pl->d_key, P);
+    pl->n_ints = 2 + 2 * qp::kKeyBins + 2;
+    ALLOC(pl->d_ints, pl->n_ints);
+    ALLOC(pl->d_bin_start, qp::kKeyBins);
+    ALLOC(pl->d_queue, P);
+    ALLOC(pl->d_rowptr, pl->total_rows);
+    ALLOC(pl->d_nnz, P + 1);
+    ALLOC(pl->d_base, P);
+    ALLOC(pl->d_pool_col, pl->pool_cap);
+    ALLOC(pl->d_pool_val, pl->pool_cap);
+    ALLOC(pl->d_col, pl->pool_cap);
+    ALLOC(pl->d_val, pl->pool_cap);
+    ALLOC(pl->d_dist, P);
+    ALLOC(pl->d_logz, 2 * P);
+    ALLOC(pl->d_scan_tmp, qp::scan_tmp_elems(P + 1) + 8);
+    ALLOC(pl->d_scratch, (int64_t)pl->grid * qp::kWavesPerBlock * pl->args.slot_bytes);
+#undef ALLOC
+    HIP_TRY(hipMemcpy(pl->d_lens, pl->lens.data(), sizeof(int32_t) * pl->n, hipMemcpyHostToDevice));
+    if (!pl->all_pairs) {
+        HIP_TRY(hipMemcpy(pl->d_list_i, pl->list_i.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(pl->d_list_j, pl->list_j.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+    }
+    qp::DevParams dp{};
+    std::memcpy(dp.joint, pl->params.joint, sizeof(dp.joint));
+    std::memcpy(dp.score, pl->params.score, sizeof(dp.score));
+    for (int k = 0; k < 2; ++k) {
+        dp.gap_open[k] = k < pl->params.n_gap_classes ? pl->params.gap_open[k] : 0.0;
+        dp.gap_extend[k] = k < pl->params.n_gap_classes ? pl->params.gap_extend[k] : 0.0;
+    }
+    dp.pf_gap_open = pl->params.pf_gap_open;
+    dp.pf_gap_extend = pl->params.pf_gap_extend;
+    dp.temperature = pl->params.temperature;
+    dp.w_hmm = pl->params.w_hmm;
+    dp.n_gap_classes = pl->params.n_gap_classes;
+    HIP_TRY(hipMemcpy(pl->d_params, &dp, sizeof(dp), hipMemcpyHostToDevice));
+
+    qp::PairArgs& a = pl->args;
+    a.lens = pl->d_lens;
+    a.pair_i = pl->d_pi;
+    a.pair_j = pl->d_pj;
+    a.queue = pl->d_queue;
+    a.n_pairs = P;
+    a.queue_head = pl->d_ints;
+    a.tab = pl->d_tab;
+    a.consts = pl->d_consts;
+    a.thresh = pl->thresh;
+    a.cap = pl->cap;
+    a.row_off = pl->d_rowoff;
+    a.row_ptr = pl->d_rowptr;
+    a.pair_nnz = pl->d_nnz;
+    a.pair_base = pl->d_base;
+    a.pool_col = pl->d_pool_col;
+    a.pool_val = pl->d_pool_val;
+    a.pool_cap = pl->pool_cap;
+    a.pool_head = reinterpret_cast<unsigned long long*>(pl->d_ints + 2 + 2 * qp::kKeyBins);
+    a.dist = pl->d_dist;
+    a.logz = pl->d_logz;
+    a.flags = pl->d_ints + 1;
+    a.scratch = pl->d_scratch;
+    return QP_OK;
+}
+
+// enqueue every step of the pipeline on s (eager); events optional
+static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, hipEvent_t* ev) {
+    const int64_t P = pl->P;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(qp::launch_reset(pl->d_ints, pl->n_ints, s));
+    HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->fp64, s));
+    HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
+                             pl->d_key, pl->d_ints + 2, pl->d_nnz, s));
+    HIP_TRY(qp::launch_bins(pl->d_ints + 2, pl->d_bin_start, s));
+    HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + 2 + qp::kKeyBins, pl->d_queue, s));
+    HIP_TRY(qp::scan_i64(pl->d_rowoff, P + 1, pl->d_scan_tmp, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(qp::launch_pairs(pl->rmax, pl->fp64, pl->grid, pl->args, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(qp::scan_i64(pl->d_nnz, P + 1, pl->d_scan_tmp, s));
+    HIP_TRY(qp::launch_gather(P, pl->d_nnz, pl->d_base, pl->d_pool_col, pl->d_pool_val, pl->d_col,
+                              pl->d_val, pl->pool_cap, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return QP_OK;
+}
+
+static qp_status capture_graphs(qp_plan* pl) {
+    for (int g = 0; g < kNumEventSets; ++g) {
+        if (pl->exec[g]) {
+            hipGraphExecDestroy(pl->exec[g]);
+            pl->exec[g] = nullptr;
+        }
+    }
+    for (int g = 0; g < kNumEventSets; ++g) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(QP_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        qp_status st = enqueue_pipeline(pl, pl->cap_stream, pl->ev[g]);
+        e = hipStreamEndCapture(pl->cap_stream, &graph);
+        if (st != QP_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(QP_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&pl->exec[g], graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(QP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return QP_OK;
+}
+
+static void collect_timing(qp_plan* pl) {
+    for (int g = 0; g < kNumEventSets; ++g) {
+        if (!pl->ev_pending[g]) continue;
+        float k = 0.f, p = 0.f;
+        if (hipEventElapsedTime(&k, pl->ev[g][1], pl->ev[g][2]) == hipSuccess &&
+            hipEventElapsedTime(&p, pl->ev[g][0], pl->ev[g][3]) == hipSuccess) {
+            pl->sum_kernel_ms += k;
+            pl->sum_pipe_ms += p;
+            pl->n_timed += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        pl->ev_pending[g] = false;
+    }
+}
+
+extern "C" {
+
+int32_t qp_version(void) { return (1 << 16) | 0; }
+
+const char* qp_last_error(void) { return g_err.c_str(); }
+
+void qp_params_default(qp_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->n_gap_classes = 2;
+    p->gap_open[0] = 0.02;
+    p->gap_open[1] = 0.005;
+    p->gap_extend[0] = 0.5;
+    p->gap_extend[1] = 0.9;
+    p->pf_gap_open = -12.0;
+    p->pf_gap_extend = -1.0;
+    p->temperature = 5.0;
+    p->w_hmm = 0.5;
+    p->precision = QP_FP32_SCALED;
+}
+
+qp_status qp_params_check(const qp_params* p) {
+    if (!p) return fail(QP_EINVAL, "params is NULL");
+    double s = 0.0;
+    for (int i = 0; i < QP_ALPHA * QP_ALPHA; ++i) {
+        const double v = p->joint[i];
+        if (!(v > 0.0 && v < 1.0)) return fail(QP_EINVAL, "joint[%d] = %g is not in (0,1)", i, v);
+        s += v;
+        if (!std::isfinite(p->score[i])) return fail(QP_EINVAL, "score[%d] is not finite", i);
+    }
+    if (std::fabs(s - 1.0) > 1e-9) return fail(QP_EINVAL, "joint sums to %.17g, not 1", s);
+    if (!is_sym(p->joint, 1e-12)) return fail(QP_EINVAL, "joint is not symmetric");
+    if (!is_sym(p->score, 1e-12)) return fail(QP_EINVAL, "score is not symmetric");
+    if (p->n_gap_classes < 1 || p->n_gap_classes > QP_MAX_GAP_CLASSES)
+        return fail(QP_EINVAL, "n_gap_classes = %d (must be 1 or 2)", p->n_gap_classes);
+    double tau = 1.0;
+    for (int k = 0; k < p->n_gap_classes; ++k) {
+        if (!(p->gap_open[k] > 0.0 && p->gap_open[k] < 0.5))
+            return fail(QP_EINVAL, "gap_open[%d] = %g is not in (0, 0.5)", k, p->gap_open[k]);
+        if (!(p->gap_extend[k] >= 0.0 && p->gap_extend[k] < 1.0))
+            return fail(QP_EINVAL, "gap_extend[%d] = %g is not in [0, 1)", k, p->gap_extend[k]);
+        tau -= 2.0 * p->gap_open[k];
+    }
+    if (!(tau > 0.0)) return fail(QP_EINVAL, "1 - 2*sum(gap_open) = %g must be > 0", tau);
+    if (!(p->temperature > 0.0) || !std::isfinite(p->temperature))
+        return fail(QP_EINVAL, "temperature = %g must be > 0", p->temperature);
+    if (!std::isfinite(p->pf_gap_open) || !std::isfinite(p->pf_gap_extend))
+        return fail(QP_EINVAL, "PF gap scores must be finite");
+    if (!(p->w_hmm >= 0.0 && p->w_hmm <= 1.0)) return fail(QP_EINVAL, "w_hmm = %g is not in [0,1]", p->w_hmm);
+    if (p->precision != QP_FP32_SCALED && p->precision != QP_FP64)
+        return fail(QP_EINVAL, "precision = %d is unknown", p->precision);
+    // the kernels hold per-residue weights in the working precision
+    const double lim = p->precision == QP_FP64 ? 600.0 : 80.0;
+    for (int i = 0; i < QP_ALPHA * QP_ALPHA; ++i)
+        if (std::fabs(p->score[i] / p->temperature) > lim)
+            return fail(QP_EINVAL, "score[%d]/T = %g is outside the representable weight range", i,
+                        p->score[i] / p->temperature);
+    if (std::fabs(p->pf_gap_open / p->temperature) > lim || std::fabs(p->pf_gap_extend / p->temperature) > lim)
+        return fail(QP_EINVAL, "PF gap score / T is outside the representable weight range");
+    return QP_OK;
+}
+
+qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                         int64_t n_pairs, const qp_params* params, float thresh, int64_t nnz_capacity,
+                         qp_plan** plan) {
+    if (!plan) return fail(QP_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    qp_status st = validate_lens(lens, n);
+    if (st != QP_OK) return st;
+    if ((st = qp_params_check(params)) != QP_OK) return st;
+    if (!(thresh > 0.0f && thresh <= 1.0f)) return fail(QP_EINVAL, "thresh = %g is not in (0, 1]", (double)thresh);
+    const bool all = pair_i == nullptr && pair_j == nullptr;
+    if (!all) {
+        if (!pair_i || !pair_j) return fail(QP_EINVAL, "pair_i and pair_j must both be given");
+        if (n_pairs < 0) return fail(QP_EINVAL, "n_pairs < 0");
+        for (int64_t k = 0; k < n_pairs; ++k) {
+            if (pair_i[k] < 0 || pair_i[k] >= n || pair_j[k] < 0 || pair_j[k] >= n)
+                return fail(QP_EINVAL, "pair %lld = (%d, %d) is out of range", (long long)k, pair_i[k], pair_j[k]);
+            if (pair_i[k] == pair_j[k])
+                return fail(QP_EINVAL, "pair %lld pairs sequence %d with itself", (long long)k, pair_i[k]);
+        }
+    }
+    const int64_t P = all ? (int64_t)n * (n - 1) / 2 : n_pairs;
+    if (P > INT32_MAX) return fail(QP_EINVAL, "%lld pairs exceed the 2^31 limit of one plan", (long long)P);
+    int dev = 0, n_cu = 0;
+    if ((st = check_device(&dev, &n_cu)) != QP_OK) return st;
+
+    qp_plan* pl = new (std::nothrow) qp_plan();
+    if (!pl) return fail(QP_ENOMEM, "out of host memory");
+    pl->device = dev;
+    pl->n = n;
+    pl->P = P;
+    pl->all_pairs = all;
+    pl->lens.assign(lens, lens + n);
+    if (!all) {
+        pl->list_i.assign(pair_i, pair_i + P);
+        pl->list_j.assign(pair_j, pair_j + P);
+    }
+    pl->params = *params;
+    pl->thresh = thresh;
+    pl->fp64 = params->precision == QP_FP64 ? 1 : 0;
+
+    // shape of the work: longest rows / columns over the pairs
+    int mmax = 1, nmax = 1;
+    int64_t rows = 0, est = 0;
+    const double inv = std::floor(1.0 / (double)thresh);
+    const int per_row = (int)std::max(1.0, std::min(8.0, inv));
+    if (all) {
+        for (int32_t i = 0; i + 1 < n; ++i) {
+            mmax = std::max(mmax, lens[i]);
+            rows += (int64_t)(n - 1 - i) * (lens[i] + 1);
+        }
+        for (int32_t j = 1; j < n; ++j) nmax = std::max(nmax, lens[j]);
+        for (int32_t i = 0; i + 1 < n; ++i)
+            for (int32_t j = i + 1; j < n; ++j) est += (int64_t)lens[i] * std::min(per_row, lens[j]);
+    } else {
+        for (int64_t k = 0; k < P; ++k) {
+            const int32_t m = lens[pair_i[k]], c = lens[pair_j[k]];
+            mmax = std::max(mmax, m);
+            nmax = std::max(nmax, c);
+            rows += m + 1;
+            est += (int64_t)m * std::min(per_row, c);
+        }
+    }
+    pl->mmax = mmax;
+    pl->nmax = nmax;
+    pl->total_rows = rows;
+    pl->rmax = std::min(qp::kRMax, std::max(1, (mmax + qp::kWave - 1) / qp::kWave));
+    pl->nb_max = (mmax + qp::kWave * pl->rmax - 1) / (qp::kWave * pl->rmax);
+    pl->cap = (int)std::max(1.0, std::min((double)nmax, inv + 1.0));
+    pl->pool_cap = nnz_capacity > 0 ? nnz_capacity : std::max<int64_t>(est + 1024, 1024);
+    size_slot(pl);
+
+    // persistent grid: enough waves to fill every SIMD at the kernel's
+    // occupancy, bounded by the pair count and by a scratch budget
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = (size_t)64 << 30;
+    }
+    const int per_cu = qp::pairs_blocks_per_cu(pl->rmax, pl->fp64);
+    int64_t grid = (int64_t)per_cu * n_cu;
+    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (P + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock));
+    const int64_t budget = (int64_t)(free_b / 2);
+    const int64_t per_block = pl->args.slot_bytes * qp::kWavesPerBlock;
+    if (grid * per_block > budget) grid = std::max<int64_t>(1, budget / per_block);
+    pl->grid = (int)grid;
+
+    if ((st = plan_alloc_all(pl)) != QP_OK) {
+        plan_free_device(pl);
+        delete pl;
+        return st;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        for (int g = 0; g < kNumEventSets && e == hipSuccess; ++g)
+            for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipEventCreate(&pl->ev[g][q]);
+    }
+    if (e != hipSuccess) {
+        plan_free_device(pl);
+        delete pl;
+        return fail(QP_EDEVICE, "stream/event creation failed: %s", hipGetErrorString(e));
+    }
+    trace("plan: n=%d pairs=%lld rmax=%d bands<=%d mmax=%d nmax=%d cap=%d grid=%d slot=%lld B pool=%lld fp64=%d",
+          n, (long long)P, pl->rmax, pl->nb_max, mmax, nmax, pl->cap, pl->grid, (long long)pl->args.slot_bytes,
+          (long long)pl->pool_cap, pl->fp64);
+    *plan = pl;
+    return QP_OK;
+}
+
+qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_off, void* stream) {
+    if (!pl) return fail(QP_EINVAL, "plan is NULL");
+    if (pl->n > 0 && (!d_seqs || !d_seq_off)) return fail(QP_EINVAL, "device sequence pointers are NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(pl->device));
+    // results of the previous run must be read before its events are reused
+    const int g = pl->run_idx % kNumEventSets;
+    if (pl->ev_pending[g]) {
+        HIP_TRY(hipEventSynchronize(pl->ev[g][3]));
+        collect_timing(pl);
+    }
+    pl->args.seqs = d_seqs;
+    pl->args.seq_off = d_seq_off;
+    pl->last_stream = s;
+    pl->ran = true;
+    if (pl->P == 0) return QP_OK;
+    if (pl->use_graph && !pl->graph_broken) {
+        if (pl->cap_seqs != d_seqs || pl->cap_off != d_seq_off || !pl->exec[0]) {
+            trace("run: capturing graphs");
+            qp_status st = capture_graphs(pl);
+            trace("run: capture %s%s", st == QP_OK ? "ok" : "failed: ", st == QP_OK ? "" : g_err.c_str());
+            if (st != QP_OK) {
+                pl->graph_broken = true;  // fall back to eager launches
+                (void)hipGetLastError();
+            } else {
+                pl->cap_seqs = d_seqs;
+                pl->cap_off = d_seq_off;
+            }
+        }
+        if (!pl->graph_broken) {
+            trace("run: graph %d", g);
+            HIP_TRY(hipGraphLaunch(pl->exec[g], s));
+            pl->ev_pending[g] = true;
+            pl->run_idx++;
+            return QP_OK;
+        }
+    }
+    trace("run: eager (event set %d)", g);
+    qp_status st = enqueue_pipeline(pl, s, pl->ev[g]);
+    if (st != QP_OK) return st;
+    pl->ev_pending[g] = true;
+    pl->run_idx++;
+    return QP_OK;
+}
+
+qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
+    if (!pl) return fail(QP_EINVAL, "plan is NULL");
+    if (!pl->ran) return fail(QP_EINVAL, "plan has not been run");
+    HIP_TRY(hipSetDevice(pl->device));
+    trace("sync: waiting");
+    HIP_TRY(hipStreamSynchronize(pl->last_stream));
+    int64_t nnz = 0;
+    int flags = 0;
+    if (pl->P > 0) {
+        HIP_TRY(hipMemcpy(&nnz, pl->d_nnz + pl->P, sizeof(int64_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&flags, pl->d_ints + 1, sizeof(int), hipMemcpyDeviceToHost));
+    }
+    pl->last_nnz = nnz;
+    trace("sync: done nnz=%lld flags=%d", (long long)nnz, flags);
+    if (flags & 2)
+        return fail(QP_EDEVICE, "a row held more than %d entries above the threshold (staging capacity)", pl->cap);
+    if ((flags & 1) || nnz > pl->pool_cap) {
+        // grow the sparse output so that the next run fits
+        const int64_t need = nnz + nnz / 16 + 1024;
+        void* p[4] = {};
+        for (int q = 0; q < 4; ++q) {
+            hipError_t e = hipMalloc(&p[q], (size_t)need * 4);
+            if (e != hipSuccess) {
+                for (int r = 0; r < q; ++r) hipFree(p[r]);
+                (void)hipGetLastError();
+                return fail(QP_ENOMEM, "cannot grow the sparse output to %lld entries", (long long)need);
+            }
+        }
+        void* old[4] = {pl->d_pool_col, pl->d_pool_val, pl->d_col, pl->d_val};
+        for (int q = 0; q < 4; ++q) {
+            auto it = std::find(pl->allocs.begin(), pl->allocs.end(), old[q]);
+            if (it != pl->allocs.end()) {
+                hipFree(*it);
+                *it = p[q];
+            }
+        }
+        pl->device_bytes += 4 * 4 * (need - pl->pool_cap);
+        pl->d_pool_col = (int32_t*)p[0];
+        pl->d_pool_val = (float*)p[1];
+        pl->d_col = (int32_t*)p[2];
+        pl->d_val = (float*)p[3];
+        pl->pool_cap = need;
+        pl->args.pool_col = pl->d_pool_col;
+        pl->args.pool_val = pl->d_pool_val;
+        pl->args.pool_cap = need;
+        pl->cap_seqs = nullptr;  // recapture with the new buffers
+        return fail(QP_ENOSPC, "sparse output needed %lld entries; capacity grown, run again", (long long)nnz);
+    }
+    if (res) {
+        res->n_pairs = pl->P;
+        res->total_rows = pl->total_rows;
+        res->nnz = nnz;
+        res->pair_i = pl->d_pi;
+        res->pair_j = pl->d_pj;
+        res->row_off = pl->d_rowoff;
+        res->row_ptr = pl->d_rowptr;
+        res->nnz_off = pl->d_nnz;
+        res->col = pl->d_col;
+        res->val = pl->d_val;
+        res->dist = pl->d_dist;
+        res->log_z = pl->d_logz;
+    }
+    return QP_OK;
+}
+
+qp_status qp_plan_download(qp_plan* pl, qp_result** out) {
+    if (!out) return fail(QP_EINVAL, "out is NULL");
+    *out = nullptr;
+    qp_device_result d;
+    qp_status st = qp_plan_sync(pl, &d);
+    if (st != QP_OK) return st;
+    qp_result* r = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
+    if (!r) return fail(QP_ENOMEM, "out of host memory");
+    const int64_t P = pl->P;
+    r->n_seqs = pl->n;
+    r->n_pairs = P;
+    r->total_rows = pl->total_rows;
+    r->nnz = d.nnz;
+    r->pair_i = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
+    r->pair_j = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
+    r->row_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
+    r->row_ptr = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(pl->total_rows, 1));
+    r->nnz_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
+    r->col = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(d.nnz, 1));
+    r->val = (float*)std::malloc(sizeof(float) * std::max<int64_t>(d.nnz, 1));
+    r->dist = (double*)std::malloc(sizeof(double) * std::max<int64_t>(P, 1));
+    r->log_z = (double*)std::malloc(sizeof(double) * std::max<int64_t>(2 * P, 1));
+    if (!r->pair_i || !r->pair_j || !r->row_off || !r->row_ptr || !r->nnz_off || !r->col || !r->val || !r->dist ||
+        !r->log_z) {
+        qp_result_free(r);
+        return fail(QP_ENOMEM, "out of host memory");
+    }
+    if (P == 0) {
+        r->row_off[0] = 0;
+        r->nnz_off[0] = 0;
+        *out = r;
+        return QP_OK;
+    }
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t b) {
+        if (e == hipSuccess && b) e = hipMemcpy(dst, src, b, hipMemcpyDeviceToHost);
+    };
+    cp(r->pair_i, d.pair_i, sizeof(int32_t) * P);
+    cp(r->pair_j, d.pair_j, sizeof(int32_t) * P);
+    cp(r->row_off, d.row_off, sizeof(int64_t) * (P + 1));
+    cp(r->row_ptr, d.row_ptr, sizeof(int32_t) * pl->total_rows);
+    cp(r->nnz_off, d.nnz_off, sizeof(int64_t) * (P + 1));
+    cp(r->col, d.col, sizeof(int32_t) * d.nnz);
+    cp(r->val, d.val, sizeof(float) * d.nnz);
+    cp(r->dist, d.dist, sizeof(double) * P);
+    cp(r->log_z, d.log_z, sizeof(double) * 2 * P);
+    if (e != hipSuccess) {
+        qp_result_free(r);
+        return fail(QP_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
+    }
+    collect_timing(pl);
+    r->device_ms = pl->n_timed ? pl->sum_pipe_ms / pl->n_timed : 0.0;
+    *out = r;
+    return QP_OK;
+}
+
+qp_status qp_plan_timing(qp_plan* pl, double* kernel_ms, double* pipeline_ms, int64_t* n_runs, int32_t reset) {
+    if (!pl) return fail(QP_EINVAL, "plan is NULL");
+    HIP_TRY(hipSetDevice(pl->device));
+    if (pl->ran) HIP_TRY(hipStreamSynchronize(pl->last_stream));
+    collect_timing(pl);
+    if (kernel_ms) *kernel_ms = pl->n_timed ? pl->sum_kernel_ms / pl->n_timed : 0.0;
+    if (pipeline_ms) *pipeline_ms = pl->n_timed ? pl->sum_pipe_ms / pl->n_timed : 0.0;
+    if (n_runs) *n_runs = pl->n_timed;
+    if (reset) {
+        pl->sum_kernel_ms = pl->sum_pipe_ms = 0.0;
+        pl->n_timed = 0;
+    }
+    return QP_OK;
+}
+
+qp_status qp_plan_set_graph(qp_plan* pl, int32_t use_graph) {
+    if (!pl) return fail(QP_EINVAL, "plan is NULL");
+    pl->use_graph = use_graph != 0;
+    return QP_OK;
+}
+
+int64_t qp_plan_device_bytes(const qp_plan* pl) { return pl ? pl->device_bytes : 0; }
+
+void qp_plan_destroy(qp_plan* pl) {
+    if (!pl) return;
+    hipSetDevice(pl->device);
+    if (pl->ran && pl->last_stream) hipStreamSynchronize(pl->last_stream);
+    plan_free_device(pl);
+    for (int g = 0; g < kNumEventSets; ++g)
+        for (int q = 0; q < 4; ++q)
+            if (pl->ev[g][q]) hipEventDestroy(pl->ev[g][q]);
+    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
+    delete pl;
+}
+
+void qp_result_free(qp_result* r) {
+    if (!r) return;
+    std::free(r->pair_i);
+    std::free(r->pair_j);
+    std::free(r->row_off);
+    std::free(r->row_ptr);
+    std::free(r->nnz_off);
+    std::free(r->col);
+    std::free(r->val);
+    std::free(r->dist);
+    std::free(r->log_z);
+    std::free(r);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- blocking host calls
+static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32_t n, const int32_t* pi,
+                          const int32_t* pj, int64_t np, const qp_params* params, float thresh, qp_result** out) {
+    if (!out) return fail(QP_EINVAL, "out is NULL");
+    *out = nullptr;
+    qp_status st = validate_lens(lens, n);
+    if (st != QP_OK) return st;
+    if (n > 0 && !seqs) return fail(QP_EINVAL, "seqs is NULL");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!seqs[i]) return fail(QP_EINVAL, "seqs[%d] is NULL", i);
+        for (int32_t c = 0; c < lens[i]; ++c)
+            if (seqs[i][c] >= QP_ALPHA)
+                return fail(QP_EINVAL, "seqs[%d][%d] = %d is not a residue code 0..19", i, c, seqs[i][c]);
+    }
+    if ((st = qp_params_check(params)) != QP_OK) return st;
+    if (!(thresh > 0.0f && thresh <= 1.0f)) return fail(QP_EINVAL, "thresh = %g is not in (0, 1]", (double)thresh);
+    const int64_t P = pi ? np : (int64_t)n * (n - 1) / 2;
+    if (pi && np < 0) return fail(QP_EINVAL, "n_pairs < 0");
+    if (P == 0) {
+        // nothing to compute: an empty result, without touching the device
+        qp_result* r = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
+        if (!r) return fail(QP_ENOMEM, "out of host memory");
+        r->n_seqs = n;
+        r->row_off = (int64_t*)std::calloc(1, sizeof(int64_t));
+        r->nnz_off = (int64_t*)std::calloc(1, sizeof(int64_t));
+        if (!r->row_off || !r->nnz_off) {
+            qp_result_free(r);
+            return fail(QP_ENOMEM, "out of host memory");
+        }
+        *out = r;
+        return QP_OK;
+    }
+    qp_plan* pl = nullptr;
+    if ((st = qp_plan_create(lens, n, pi, pj, np, params, thresh, 0, &pl)) != QP_OK) return st;
+    std::vector<int64_t> off(std::max(n, 1));
+    int64_t tot = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        off[i] = tot;
+        tot += lens[i];
+    }
+    uint8_t* h = nullptr;
+    uint8_t* d = nullptr;
+    int64_t* d_off = nullptr;
+    hipStream_t s = nullptr;
+    auto cleanup = [&]() {
+        if (s) hipStreamSynchronize(s);
+        if (h) hipHostFree(h);
+        if (d) hipFree(d);
+        if (d_off) hipFree(d_off);
+        qp_plan_destroy(pl);
+        if (s) hipStreamDestroy(s);
+    };
+    hipError_t e = hipHostMalloc((void**)&h, (size_t)std::max<int64_t>(tot, 1), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&d, (size_t)std::max<int64_t>(tot, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&d_off, sizeof(int64_t) * std::max(n, 1));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(QP_ENOMEM, "device staging allocation failed: %s", hipGetErrorString(e));
+    }
+    for (int32_t i = 0; i < n; ++i) std::memcpy(h + off[i], seqs[i], (size_t)lens[i]);
+    e = hipMemcpyAsync(d, h, (size_t)std::max<int64_t>(tot, 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * std::max(n, 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(QP_EDEVICE, "host-to-device copy failed: %s", hipGetErrorString(e));
+    }
+    st = qp_plan_run(pl, d, d_off, s);
+    if (st == QP_OK) st = qp_plan_download(pl, out);
+    if (st == QP_ENOSPC) {
+        // the sparse output outgrew the estimate: a fresh plan sized exactly
+        const int64_t need = pl->last_nnz + 1024;
+        trace("host: retry with capacity %lld", (long long)need);
+        hipStreamSynchronize(s);
+        qp_plan_destroy(pl);
+        pl = nullptr;
+        st = qp_plan_create(lens, n, pi, pj, np, params, thresh, need, &pl);
+        if (st == QP_OK) st = qp_plan_run(pl, d, d_off, s);
+        if (st == QP_OK) st = qp_plan_download(pl, out);
+    }
+    std::string keep = g_err;
+    cleanup();
+    g_err = keep;
+    return st;
+}
+
+extern "C" qp_status qp_posteriors(const uint8_t* const* seqs, const int32_t* lens, int32_t n,
+                                   const qp_params* params, float thresh, qp_result** out) {
+    return run_host(seqs, lens, n, nullptr, nullptr, 0, params, thresh, out);
+}
+
+extern "C" qp_status qp_posteriors_pairs(const uint8_t* const* seqs, const int32_t* lens, int32_t n,
+                                         const int32_t* pair_i, const int32_t* pair_j, int64_t n_pairs,
+                                         const qp_params* params, float thresh, qp_result** out) {
+    if (!pair_i || !pair_j) {
+        if (out) *out = nullptr;
+        return fail(QP_EINVAL, "pair_i / pair_j are NULL");
+    }
+    return run_host(seqs, lens, n, pair_i, pair_j, n_pairs, params, thresh, out);
+}

@@ -1,0 +1,907 @@
+// gfx950 kernels of the all-pairs posterior engine (stage I of QuickProbs 2:
+// posterior matrices of every pair from a pair-HMM and a partition function,
+// Methods, opening paragraph; sparse storage, "Selective consistency"
+// footnote; maximum-expected-accuracy scores for the distances).
+//
+// Layout of one pair on one wavefront
+// -----------------------------------
+// Rows (residues of x) are striped over the 64 lanes: lane l owns rows
+// l*R .. l*R+R-1 of a band of 64*R rows; longer x is cut into bands processed
+// one after the other.  Columns (residues of y) are swept in a skewed
+// wavefront: at step s lane l handles column j = s - l + 1, so the row above
+// its strip (lane l-1) finished column j one step earlier and hands its last
+// row over with one DPP wave shift.  The backward pass runs the same skew in
+// the opposite direction (lane l+1 leads).
+//
+// Numbers.  Values are FP32 (or FP64) with a power-of-two scale per lane and
+// model: the stored value is true * 2^-E.  Values received from a neighbour
+// are re-based with ldexp, all lanes rescale together every kRescaleEvery
+// steps, and exponents are exact integers, so Z and the posteriors carry no
+// rounding from the scaling itself.
+//
+// Posteriors need the forward match value at the same cell as the backward
+// one; the forward pass stores (f_hmm, f_pf) per cell, step-major and lane-
+// contiguous, so both the store and the reversed read are fully coalesced.
+// The backward pass fuses the posterior, the average of the two models, the
+// threshold, the per-row staging of CSR entries and the reverse MEA recursion.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "qp_internal.h"
+
+namespace qp {
+
+template <typename T> struct Pair2;
+template <> struct Pair2<float> { using type = float2; };
+template <> struct Pair2<double> { using type = double2; };
+
+// forward boundary record: last row of a band at one column
+template <typename T> struct FwdBnd {
+    T M, U1, U2, D, gM, gU, gD;
+    int EH, EP;
+};
+// backward boundary record: first row of a band at one column
+template <typename T> struct BwdBnd {
+    T U1, U2, Tt, gU, gT;
+    double A;
+    int FH, FP;
+};
+
+template <typename T> struct Coef {
+    T tau, eps1, eps2, c1, c2, u, o;
+};
+
+// ---------------------------------------------------------------- helpers
+constexpr int kDppWaveShr1 = 0x138;  // lane l reads lane l-1
+constexpr int kDppWaveShl1 = 0x130;  // lane l reads lane l+1
+
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL));
+    int hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float qldexp(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+__device__ __forceinline__ double qldexp(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
+__device__ __forceinline__ int qexp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+__device__ __forceinline__ int qexp(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ __forceinline__ float qmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double qmax(double a, double b) { return fmax(a, b); }
+
+// 2^(e*lg - sh) with 0^0 = 1 (lg = log2 of a base that may be 0)
+__device__ __forceinline__ double pow2s(double lg, int e, int sh) {
+    return e == 0 ? exp2(-(double)sh) : exp2((double)e * lg - (double)sh);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- forward
+// One band of rows [r0, r0+rows) of pair (x, y); L lanes carry R rows each.
+template <int R, typename T>
+__device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* __restrict__ y, int n, int r0,
+                         int rows, int L, bool first, bool last, const typename Pair2<T>::type* tab,
+                         const Coef<T>& k, const double lg_eps1, const double lg_eps2, const double lg_u,
+                         const double lg_c1, const double lg_c2, const double lg_o,
+                         typename Pair2<T>::type* __restrict__ spill, int2* __restrict__ exps,
+                         const FwdBnd<T>* __restrict__ fin, FwdBnd<T>* __restrict__ fout, T& zH, T& zP,
+                         int& ezH, int& ezP) {
+    using V2 = typename Pair2<T>::type;
+    const bool used = lane < L;
+    int xo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int row = lane * R + r;
+        xo[r] = (used && row < rows ? (int)x[r0 + row] : kPadCode) * kTabW;
+    }
+    // carried per row: M, V1, V2 (horizontal), D (into-M sum for the diagonal)
+    T M[R], V1[R], V2r[R], D[R], gM[R], gV[R], gD[R];
+    int EH, EP;
+    {
+        // column 0: only vertical gap runs from the virtual begin state
+        // U_k(i,0) = eps_k^(i-1), D(i,0) = c1 U1 + c2 U2; PF alike with u, o
+        double lgH = -INFINITY, lgP = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i0 = r0 + lane * R + r;  // = i - 1
+            double a1 = (i0 == 0 ? 0.0 : (double)i0 * lg_eps1) + lg_c1;
+            double a2 = (i0 == 0 ? 0.0 : (double)i0 * lg_eps2) + lg_c2;
+            double ap = (i0 == 0 ? 0.0 : (double)i0 * lg_u) + lg_o;
+            lgH = fmax(lgH, fmax(a1, a2));
+            lgP = fmax(lgP, ap);
+        }
+        EH = isfinite(lgH) ? (int)floor(lgH) : 0;
+        EP = isfinite(lgP) ? (int)floor(lgP) : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i0 = r0 + lane * R + r;
+            double u1 = pow2s(lg_eps1, i0, EH), u2 = pow2s(lg_eps2, i0, EH), gu = pow2s(lg_u, i0, EP);
+            M[r] = T(0);
+            V1[r] = T(0);
+            V2r[r] = T(0);
+            gM[r] = T(0);
+            gV[r] = T(0);
+            D[r] = (T)((double)k.c1 * u1 + (double)k.c2 * u2);
+            gD[r] = (T)((double)k.o * gu);
+        }
+    }
+    // what this lane hands to the lane below: its last row at its current column
+    T oM = T(0), oU1 = T(0), oU2 = T(0), oD = D[R - 1], ogM = T(0), ogU = T(0), ogD = gD[R - 1];
+    int oEH = EH, oEP = EP;
+    // diagonal input of the strip's first row (row above, previous column)
+    T aD = T(0), gaD = T(0);
+    // virtual row 0 (first band, lane 0): V_k(0,j) = eps_k^(j-1), j >= 1
+    T tv1 = T(0), tv2 = T(0), tgv = T(0);
+    if (lane == 0) {
+        if (first) {
+            aD = qldexp(k.tau, -EH);     // D(0,0): the begin state
+            gaD = qldexp(T(1), -EP);
+            tv1 = qldexp(T(1), -EH);
+            tv2 = tv1;
+            tgv = qldexp(T(1), -EP);
+        } else {
+            FwdBnd<T> b = fin[0];
+            aD = qldexp(b.D, b.EH - EH);
+            gaD = qldexp(b.gD, b.EP - EP);
+        }
+    }
+    if (!last && lane == L - 1) {
+        FwdBnd<T> b;
+        b.M = T(0); b.U1 = T(0); b.U2 = T(0); b.D = D[R - 1];
+        b.gM = T(0); b.gU = T(0); b.gD = gD[R - 1];
+        b.EH = EH; b.EP = EP;
+        fout[0] = b;
+    }
+
+    const int S = n + L - 1;
+    int jn = 1 - lane;  // column of step 0
+    int ycur = (used && jn >= 1 && jn <= n) ? (int)y[jn - 1] : 0;
+    FwdBnd<T> bnext;
+    if (!first && lane == 0) bnext = fin[1 <= n ? 1 : n];
+    for (int s = 0; s < S; ++s) {
+        const int j = s - lane + 1;
+        const bool active = used && j >= 1 && j <= n;
+        int ynext = (used && j + 1 >= 1 && j + 1 <= n) ? (int)y[j] : 0;
+        FwdBnd<T> bcur = bnext;
+        if (!first && lane == 0) bnext = fin[s + 2 <= n ? s + 2 : n];
+        // ---- exchange with the lane above
+        T rM = dpp<kDppWaveShr1>(oM), rU1 = dpp<kDppWaveShr1>(oU1), rU2 = dpp<kDppWaveShr1>(oU2);
+        T rD = dpp<kDppWaveShr1>(oD), rgM = dpp<kDppWaveShr1>(ogM), rgU = dpp<kDppWaveShr1>(ogU);
+        T rgD = dpp<kDppWaveShr1>(ogD);
+        int rEH = dpp_i<kDppWaveShr1>(oEH), rEP = dpp_i<kDppWaveShr1>(oEP);
+        if (lane == 0) {
+            if (first) {
+                rM = T(0); rU1 = T(0); rU2 = T(0);
+                rD = k.c1 * tv1 + k.c2 * tv2;
+                rgM = T(0); rgU = T(0);
+                rgD = k.o * tgv;
+                rEH = EH; rEP = EP;
+                tv1 *= k.eps1; tv2 *= k.eps2; tgv *= k.u;
+            } else {
+                rM = bcur.M; rU1 = bcur.U1; rU2 = bcur.U2; rD = bcur.D;
+                rgM = bcur.gM; rgU = bcur.gU; rgD = bcur.gD;
+                rEH = bcur.EH; rEP = bcur.EP;
+            }
+        }
+        {
+            const int dH = rEH - EH, dP = rEP - EP;
+            rM = qldexp(rM, dH); rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rD = qldexp(rD, dH);
+            rgM = qldexp(rgM, dP); rgU = qldexp(rgU, dP); rgD = qldexp(rgD, dP);
+        }
+        if (active) {
+            T upM = rM, upU1 = rU1, upU2 = rU2, dg = aD;
+            T gupM = rgM, gupU = rgU, gdg = gaD;
+            V2* sp = spill + (int64_t)s * R * kWave + lane;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const V2 e = tab[xo[r] + ycur];
+                const T nM = e.x * dg;
+                const T nU1 = fma(k.eps1, upU1, upM);
+                const T nU2 = fma(k.eps2, upU2, upM);
+                const T nV1 = fma(k.eps1, V1[r], M[r]);
+                const T nV2 = fma(k.eps2, V2r[r], M[r]);
+                const T nD = fma(k.c2, nU2 + nV2, fma(k.c1, nU1 + nV1, k.tau * nM));
+                const T ngM = e.y * gdg;
+                const T ngU = fma(k.u, gupU, gupM);
+                const T ngV = fma(k.u, gV[r], gM[r]);
+                const T ngD = fma(k.o, ngU + ngV, ngM);
+                dg = D[r];
+                gdg = gD[r];
+                M[r] = nM; V1[r] = nV1; V2r[r] = nV2; D[r] = nD;
+                gM[r] = ngM; gV[r] = ngV; gD[r] = ngD;
+                upM = nM; upU1 = nU1; upU2 = nU2;
+                gupM = ngM; gupU = ngU;
+                V2 st;
+                st.x = nM;
+                st.y = ngM;
+                sp[r * kWave] = st;
+            }
+            exps[(int64_t)s * kWave + lane] = make_int2(EH, EP);
+            oM = upM; oU1 = upU1; oU2 = upU2; oD = D[R - 1];
+            ogM = gupM; ogU = gupU; ogD = gD[R - 1];
+            if (!last && lane == L - 1) {
+                FwdBnd<T> b;
+                b.M = oM; b.U1 = oU1; b.U2 = oU2; b.D = oD;
+                b.gM = ogM; b.gU = ogU; b.gD = ogD;
+                b.EH = EH; b.EP = EP;
+                fout[j] = b;
+            }
+        }
+        aD = rD;
+        gaD = rgD;
+        ycur = ynext;
+        if ((s % kRescaleEvery) == kRescaleEvery - 1) {
+            T mh = T(0), mp = T(0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                mh = qmax(mh, D[r]);
+                mp = qmax(mp, gD[r]);
+            }
+            const int sh = -qexp(mh), sp = -qexp(mp);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                M[r] = qldexp(M[r], sh); V1[r] = qldexp(V1[r], sh); V2r[r] = qldexp(V2r[r], sh);
+                D[r] = qldexp(D[r], sh);
+                gM[r] = qldexp(gM[r], sp); gV[r] = qldexp(gV[r], sp); gD[r] = qldexp(gD[r], sp);
+            }
+            oM = qldexp(oM, sh); oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh); oD = qldexp(oD, sh);
+            aD = qldexp(aD, sh); tv1 = qldexp(tv1, sh); tv2 = qldexp(tv2, sh);
+            ogM = qldexp(ogM, sp); ogU = qldexp(ogU, sp); ogD = qldexp(ogD, sp);
+            gaD = qldexp(gaD, sp); tgv = qldexp(tgv, sp);
+            EH -= sh;
+            EP -= sp;
+        }
+        oEH = EH;
+        oEP = EP;
+    }
+    if (last) {
+        // Z = D(m, n): last real row of the band, held by lane L-1
+        const int rm = (rows - 1) - (L - 1) * R;
+        T zd = T(0), zg = T(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r == rm) { zd = D[r]; zg = gD[r]; }
+        zH = rdlane(zd, L - 1);
+        zP = rdlane(zg, L - 1);
+        ezH = rdlane(EH, L - 1);
+        ezP = rdlane(EP, L - 1);
+    }
+}
+
+// --------------------------------------------------------------- backward
+template <int R, typename T>
+__device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* __restrict__ y, int n, int r0,
+                         int rows, int L, bool first, bool last, const typename Pair2<T>::type* tab,
+                         const Coef<T>& k, const typename Pair2<T>::type* __restrict__ spill,
+                         const int2* __restrict__ exps, const BwdBnd<T>* __restrict__ bin,
+                         BwdBnd<T>* __restrict__ bout, T invZH, T invZP, int ezH, int ezP, float thresh,
+                         int cap, int32_t* __restrict__ stage_col, float* __restrict__ stage_val,
+                         int32_t* __restrict__ rowcnt, int* __restrict__ flags, double& a11) {
+    using V2 = typename Pair2<T>::type;
+    const bool used = lane < L;
+    int xo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int row = lane * R + r;
+        xo[r] = (used && row < rows ? (int)x[r0 + row] : kPadCode) * kTabW;
+    }
+    // carried per row (values at column j+1): bV1, bV2 (horizontal),
+    // Tp = e * bM (diagonal input of the row above), A (reverse MEA)
+    T bV1[R], bV2[R], Tp[R], gbV[R], gTp[R];
+    double A[R];
+    int cnt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        bV1[r] = T(0); bV2[r] = T(0); Tp[r] = T(0); gbV[r] = T(0); gTp[r] = T(0);
+        A[r] = 0.0;
+        cnt[r] = 0;
+    }
+    int FH = 0, FP = 0;
+    // diagonal input of the strip's last row (row below, next column)
+    T bT = T(0), bgT = T(0);
+    double bA = 0.0;
+    if (last && lane == L - 1) {
+        // end state: the cell after (m, n) contributes weight 1 to (m, n)
+        const int rm = (rows - 1) - (L - 1) * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r == rm + 1) { Tp[r] = T(1); gTp[r] = T(1); }
+        if (rm + 1 == R) { bT = T(1); bgT = T(1); }
+    }
+    T oU1 = T(0), oU2 = T(0), oT = T(0), ogU = T(0), ogT = T(0);
+    double oA = 0.0;
+    int oFH = 0, oFP = 0;
+
+    const int S = n + L - 1;
+    const int lead = L - 1 - lane;
+    auto col_of = [&](int t) { return n - t + lead; };
+    int jc = col_of(0);
+    int ycur = (used && jc >= 1 && jc <= n) ? (int)y[jc - 1] : 0;
+    V2 fcur[R], fnext[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { fnext[r].x = T(0); fnext[r].y = T(0); }
+    int2 ecur = make_int2(0, 0), enext = make_int2(0, 0);
+    if (used && jc >= 1 && jc <= n) {
+        const V2* sp = spill + (int64_t)(S - 1) * R * kWave + lane;
+#pragma unroll
+        for (int r = 0; r < R; ++r) fcur[r] = sp[r * kWave];
+        ecur = exps[(int64_t)(S - 1) * kWave + lane];
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) { fcur[r].x = T(0); fcur[r].y = T(0); }
+    }
+    BwdBnd<T> bnext;
+    if (!last && lane == L - 1) bnext = bin[n];
+    for (int t = 0; t < S; ++t) {
+        const int j = col_of(t);
+        const bool active = used && j >= 1 && j <= n;
+        const bool nact = used && j - 1 >= 1 && j - 1 <= n;
+        // prefetch the next step's residue, forward values and boundary
+        int ynext = nact ? (int)y[j - 2] : 0;
+        if (nact) {
+            const V2* sp = spill + (int64_t)(S - 2 - t) * R * kWave + lane;
+#pragma unroll
+            for (int r = 0; r < R; ++r) fnext[r] = sp[r * kWave];
+            enext = exps[(int64_t)(S - 2 - t) * kWave + lane];
+        }
+        BwdBnd<T> bcur = bnext;
+        if (!last && lane == L - 1) bnext = bin[j - 1 >= 1 ? j - 1 : 1];
+        // ---- exchange with the lane below
+        T rU1 = dpp<kDppWaveShl1>(oU1), rU2 = dpp<kDppWaveShl1>(oU2), rT = dpp<kDppWaveShl1>(oT);
+        T rgU = dpp<kDppWaveShl1>(ogU), rgT = dpp<kDppWaveShl1>(ogT);
+        double rA = dpp<kDppWaveShl1>(oA);
+        int rFH = dpp_i<kDppWaveShl1>(oFH), rFP = dpp_i<kDppWaveShl1>(oFP);
+        if (lane == L - 1) {
+            if (last) {
+                rU1 = T(0); rU2 = T(0); rT = T(0); rgU = T(0); rgT = T(0);
+                rA = 0.0;
+                rFH = FH; rFP = FP;
+            } else {
+                rU1 = bcur.U1; rU2 = bcur.U2; rT = bcur.Tt; rgU = bcur.gU; rgT = bcur.gT;
+                rA = bcur.A;
+                rFH = bcur.FH; rFP = bcur.FP;
+            }
+        }
+        {
+            const int dH = rFH - FH, dP = rFP - FP;
+            rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rT = qldexp(rT, dH);
+            rgU = qldexp(rgU, dP); rgT = qldexp(rgT, dP);
+        }
+        if (active) {
+            T dU1 = rU1, dU2 = rU2, dgU = rgU;
+            double dA = rA;
+            T dgT = bT, dggT = bgT;
+            double dgA = bA;
+            const int kH = ecur.x + FH - ezH, kP = ecur.y + FP - ezP;
+#pragma unroll
+            for (int r = R - 1; r >= 0; --r) {
+                const V2 e = tab[xo[r] + ycur];
+                const T t1 = dgT, tg = dggT;
+                const T nU1 = fma(k.eps1, dU1, t1);
+                const T nU2 = fma(k.eps2, dU2, t1);
+                const T nV1 = fma(k.eps1, bV1[r], t1);
+                const T nV2 = fma(k.eps2, bV2[r], t1);
+                const T bM = fma(k.c2, dU2 + bV2[r], fma(k.c1, dU1 + bV1[r], k.tau * t1));
+                const T nT = e.x * bM;
+                const T ngU = fma(k.u, dgU, tg);
+                const T ngV = fma(k.u, gbV[r], tg);
+                const T gbM = fma(k.o, dgU + gbV[r], tg);
+                const T ngT = e.y * gbM;
+                const T pH = qldexp(fcur[r].x * bM * invZH, kH);
+                const T pP = qldexp(fcur[r].y * gbM * invZP, kP);
+                const T P = pH + pP;
+                const double nA = fmax(dgA + (double)P, fmax(dA, A[r]));
+                const int row = lane * R + r;
+                if (P >= (T)thresh && row < rows) {
+                    const int c = cnt[r];
+                    if (c < cap) {
+                        const int64_t at = (int64_t)(r0 + row) * cap + c;
+                        stage_col[at] = j - 1;
+                        stage_val[at] = (float)P;
+                    }
+                    cnt[r] = c + 1;
+                }
+                dgT = Tp[r]; dggT = gTp[r]; dgA = A[r];
+                Tp[r] = nT; gTp[r] = ngT; A[r] = nA;
+                bV1[r] = nV1; bV2[r] = nV2; gbV[r] = ngV;
+                dU1 = nU1; dU2 = nU2; dgU = ngU; dA = nA;
+            }
+            oU1 = dU1; oU2 = dU2; oT = Tp[0]; ogU = dgU; ogT = gTp[0]; oA = A[0];
+            if (!first && lane == 0) {
+                BwdBnd<T> b;
+                b.U1 = oU1; b.U2 = oU2; b.Tt = oT; b.gU = ogU; b.gT = ogT; b.A = oA;
+                b.FH = FH; b.FP = FP;
+                bout[j] = b;
+            }
+        }
+        bT = rT;
+        bgT = rgT;
+        bA = rA;
+        ycur = ynext;
+#pragma unroll
+        for (int r = 0; r < R; ++r) fcur[r] = fnext[r];
+        ecur = enext;
+        if ((t % kRescaleEvery) == kRescaleEvery - 1) {
+            T mh = T(0), mp = T(0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                mh = qmax(mh, qmax(Tp[r], qmax(bV1[r], bV2[r])));
+                mp = qmax(mp, qmax(gTp[r], gbV[r]));
+            }
+            const int sh = -qexp(mh), sp = -qexp(mp);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bV1[r] = qldexp(bV1[r], sh); bV2[r] = qldexp(bV2[r], sh); Tp[r] = qldexp(Tp[r], sh);
+                gbV[r] = qldexp(gbV[r], sp); gTp[r] = qldexp(gTp[r], sp);
+            }
+            oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh); oT = qldexp(oT, sh); bT = qldexp(bT, sh);
+            ogU = qldexp(ogU, sp); ogT = qldexp(ogT, sp); bgT = qldexp(bgT, sp);
+            FH -= sh;
+            FP -= sp;
+        }
+        oFH = FH;
+        oFP = FP;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = lane * R + r;
+        if (used && row < rows) {
+            int c = cnt[r];
+            if (c > cap) {
+                atomicOr(flags, 2);
+                c = cap;
+            }
+            rowcnt[r0 + row] = c;
+        }
+    }
+    if (first) a11 = rdlane(A[0], 0);
+}
+
+// ------------------------------------------------------------ one pair
+template <int R, typename T>
+__device__ void process_pair(const PairArgs& a, int lane, char* slot, const typename Pair2<T>::type* tab,
+                             const Coef<T>& k, const double* lgs, int64_t p) {
+    using V2 = typename Pair2<T>::type;
+    const int pi = a.pair_i[p], pj = a.pair_j[p];
+    const int m = a.lens[pi], n = a.lens[pj];
+    const uint8_t* x = a.seqs + a.seq_off[pi];
+    const uint8_t* y = a.seqs + a.seq_off[pj];
+    const int H = kWave * R;
+    const int nb = (m + H - 1) / H;
+    V2* spill = reinterpret_cast<V2*>(slot);
+    int2* exps = reinterpret_cast<int2*>(slot + a.off_exps);
+    FwdBnd<T>* fb = reinterpret_cast<FwdBnd<T>*>(slot + a.off_fb);
+    BwdBnd<T>* bb = reinterpret_cast<BwdBnd<T>*>(slot + a.off_bb);
+    int32_t* stage_col = reinterpret_cast<int32_t*>(slot + a.off_stage_col);
+    float* stage_val = reinterpret_cast<float*>(slot + a.off_stage_val);
+
+    T zH = T(1), zP = T(1);
+    int ezH = 0, ezP = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int r0 = b * H;
+        const int rows = min(H, m - r0);
+        const int L = (rows + R - 1) / R;
+        fwd_band<R, T>(lane, x, y, n, r0, rows, L, b == 0, b == nb - 1, tab, k, lgs[0], lgs[1], lgs[2], lgs[3],
+                       lgs[4], lgs[5], spill + (int64_t)b * a.spill_band_stride,
+                       exps + (int64_t)b * a.exps_band_stride, fb + (int64_t)((b + 1) & 1) * a.bnd_stride,
+                       fb + (int64_t)(b & 1) * a.bnd_stride, zH, zP, ezH, ezP);
+        __threadfence_block();
+    }
+    const T invZH = T(a.consts->w_hmm) / zH;
+    const T invZP = T(1.0 - a.consts->w_hmm) / zP;
+    int32_t* rp = a.row_ptr + a.row_off[p];
+    double a11 = 0.0;
+    for (int b = nb - 1; b >= 0; --b) {
+        const int r0 = b * H;
+        const int rows = min(H, m - r0);
+        const int L = (rows + R - 1) / R;
+        bwd_band<R, T>(lane, x, y, n, r0, rows, L, b == 0, b == nb - 1, tab, k,
+                       spill + (int64_t)b * a.spill_band_stride, exps + (int64_t)b * a.exps_band_stride,
+                       bb + (int64_t)((b + 1) & 1) * a.bnd_stride, bb + (int64_t)(b & 1) * a.bnd_stride, invZH,
+                       invZP, ezH, ezP, a.thresh, a.cap, stage_col, stage_val, rp + 1, a.flags, a11);
+        __threadfence_block();
+    }
+    // ---- row counts -> row pointers (inclusive scan in place)
+    int carry = 0;
+    for (int base = 0; base < m; base += kWave) {
+        const int idx = base + lane;
+        int v = idx < m ? rp[1 + idx] : 0;
+        v = wave_incl_scan(v, lane);
+        if (idx < m) rp[1 + idx] = v + carry;
+        carry += __shfl(v, kWave - 1, kWave);
+    }
+    if (lane == 0) rp[0] = 0;
+    __threadfence_block();
+    const int nnz = carry;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.pool_head, (unsigned long long)nnz);
+    base = __shfl(base, 0, kWave);
+    if (lane == 0) {
+        a.pair_nnz[p] = nnz;
+        a.pair_base[p] = (int64_t)base;
+        const double lzh = log((double)zH) + (double)ezH * 0.69314718055994530942;
+        const double lzp = log((double)zP) + (double)ezP * 0.69314718055994530942;
+        a.logz[2 * p] = lzh;
+        a.logz[2 * p + 1] = lzp;
+        a.dist[p] = 1.0 - a11 / (double)min(m, n);
+    }
+    if ((int64_t)base + nnz > a.pool_cap) {
+        if (lane == 0) atomicOr(a.flags, 1);
+        return;
+    }
+    for (int row = lane; row < m; row += kWave) {
+        const int st = rp[row];
+        const int c = rp[row + 1] - st;
+        const int64_t dst0 = (int64_t)base + st + c - 1;
+        const int64_t src0 = (int64_t)row * a.cap;
+        for (int q = 0; q < c; ++q) {
+            a.pool_col[dst0 - q] = stage_col[src0 + q];
+            a.pool_val[dst0 - q] = stage_val[src0 + q];
+        }
+    }
+    __threadfence_block();
+}
+
+template <int RR, int RMAX, typename T>
+__device__ __forceinline__ void dispatch(int R, const PairArgs& a, int lane, char* slot,
+                                         const typename Pair2<T>::type* tab, const Coef<T>& k, const double* lgs,
+                                         int64_t p) {
+    if constexpr (RR > RMAX) {
+        return;
+    } else {
+        if (R == RR)
+            process_pair<RR, T>(a, lane, slot, tab, k, lgs, p);
+        else
+            dispatch<RR + 1, RMAX, T>(R, a, lane, slot, tab, k, lgs, p);
+    }
+}
+
+template <int RMAX, typename T>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
+    using V2 = typename Pair2<T>::type;
+    __shared__ V2 tab[kTabRows * kTabW];
+    const V2* gtab = reinterpret_cast<const V2*>(a.tab);
+    for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    char* slot = a.scratch + (int64_t)wid * a.slot_bytes;
+    const DevConsts c = *a.consts;
+    Coef<T> k;
+    k.tau = (T)c.tau; k.eps1 = (T)c.eps1; k.eps2 = (T)c.eps2; k.c1 = (T)c.c1; k.c2 = (T)c.c2;
+    k.u = (T)c.u; k.o = (T)c.o;
+    // log2 of the rounded coefficients, for the closed-form column-0 values
+    double lgs[6] = {log2((double)k.eps1), log2((double)k.eps2), log2((double)k.u),
+                     log2((double)k.c1), log2((double)k.c2), log2((double)k.o)};
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(a.queue_head, 1);
+        q = __shfl(q, 0, kWave);
+        if ((int64_t)q >= a.n_pairs) break;
+        const int64_t p = a.queue[q];
+        const int m = a.lens[a.pair_i[p]];
+        int R = (m + kWave - 1) / kWave;
+        if (R > RMAX) R = RMAX;
+        dispatch<1, RMAX, T>(R, a, lane, slot, tab, k, lgs, p);
+    }
+}
+
+// ------------------------------------------------------ tables (a2 step)
+// Builds the (e_hmm, w_pf) table and the scaled constants from the raw
+// parameters in FP64, rounding once to the kernel precision.
+template <typename T>
+__global__ void k_tables(const DevParams* __restrict__ p, typename Pair2<T>::type* __restrict__ tab,
+                         DevConsts* __restrict__ c) {
+    using V2 = typename Pair2<T>::type;
+    const int t = threadIdx.x;
+    __shared__ double qx[20], qy[20];
+    if (t < 20) {
+        double sx = 0.0, sy = 0.0;
+        for (int b = 0; b < 20; ++b) {
+            sx += p->joint[t * 20 + b];
+            sy += p->joint[b * 20 + t];
+        }
+        qx[t] = sx;
+        qy[t] = sy;
+    }
+    __syncthreads();
+    for (int idx = t; idx < kTabRows * kTabW; idx += blockDim.x) {
+        const int a = idx / kTabW, b = idx % kTabW;
+        V2 v;
+        v.x = T(0);
+        v.y = T(0);
+        if (a < 20 && b < 20) {
+            v.x = (T)(p->joint[a * 20 + b] / (qx[a] * qy[b]));
+            v.y = (T)exp(p->score[a * 20 + b] / p->temperature);
+        }
+        tab[idx] = v;
+    }
+    if (t == 0) {
+        const int G = p->n_gap_classes;
+        const double d1 = p->gap_open[0], e1 = p->gap_extend[0];
+        const double d2 = G > 1 ? p->gap_open[1] : 0.0, e2 = G > 1 ? p->gap_extend[1] : 0.0;
+        DevConsts k;
+        k.tau = 1.0 - 2.0 * (d1 + d2);
+        k.eps1 = e1;
+        k.eps2 = e2;
+        k.c1 = d1 * (1.0 - e1);
+        k.c2 = d2 * (1.0 - e2);
+        k.u = exp(p->pf_gap_extend / p->temperature);
+        k.o = exp(p->pf_gap_open / p->temperature);
+        k.w_hmm = p->w_hmm;
+        *c = k;
+    }
+}
+
+// -------------------------------------------------- schedule (a1 step)
+__global__ void k_reset(int* ints, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) ints[i] = 0;
+}
+
+__device__ __forceinline__ int64_t pair_start(int64_t i, int64_t n) { return i * n - i * (i + 1) / 2; }
+
+__global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32_t* __restrict__ list_i,
+                        const int32_t* __restrict__ list_j, int64_t P, int32_t* __restrict__ pi,
+                        int32_t* __restrict__ pj, int64_t* __restrict__ rows1, int32_t* __restrict__ key,
+                        int* __restrict__ hist, int64_t* __restrict__ pair_nnz) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        rows1[P] = 0;
+        pair_nnz[P] = 0;
+    }
+    if (p >= P) return;
+    int64_t i, j;
+    if (list_i) {
+        i = list_i[p];
+        j = list_j[p];
+    } else {
+        const double nn = (double)n;
+        const double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)p;
+        i = (int64_t)floor((2.0 * nn - 1.0 - sqrt(disc > 0 ? disc : 0.0)) / 2.0);
+        if (i < 0) i = 0;
+        while (i > 0 && pair_start(i, n) > p) --i;
+        while (i + 1 < n && pair_start(i + 1, n) <= p) ++i;
+        j = p - pair_start(i, n) + i + 1;
+    }
+    pi[p] = (int32_t)i;
+    pj[p] = (int32_t)j;
+    const int64_t m = lens[i], c = lens[j];
+    rows1[p] = m + 1;
+    int kk = (int)(log2((double)(m * c)) * 16.0);
+    kk = kk < 0 ? 0 : (kk >= kKeyBins ? kKeyBins - 1 : kk);
+    key[p] = kk;
+    atomicAdd(&hist[kk], 1);
+}
+
+// exclusive offsets of the cost classes, most expensive class first
+__global__ void k_bins(const int* __restrict__ hist, int* __restrict__ bin_start) {
+    __shared__ int part[kKeyBins];
+    const int t = threadIdx.x;  // kKeyBins threads
+    part[t] = hist[kKeyBins - 1 - t];
+    __syncthreads();
+    for (int d = 1; d < kKeyBins; d <<= 1) {
+        int v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    bin_start[kKeyBins - 1 - t] = part[t] - hist[kKeyBins - 1 - t];
+}
+
+__global__ void k_fill_queue(int64_t P, const int32_t* __restrict__ key, const int* __restrict__ bin_start,
+                             int* __restrict__ bin_fill, int32_t* __restrict__ queue) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int kk = key[p];
+    const int slot = bin_start[kk] + atomicAdd(&bin_fill[kk], 1);
+    queue[slot] = (int32_t)p;
+}
+
+// ------------------------------------------------------ int64 scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__global__ void k_scan_local(int64_t* __restrict__ d, int64_t n, int64_t* __restrict__ sums) {
+    __shared__ int64_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)t * kScanItems;
+    int64_t v[kScanItems];
+    int64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t idx = base + q;
+        const int64_t x = idx < n ? d[idx] : 0;
+        v[q] = acc;
+        acc += x;
+    }
+    part[t] = acc;
+    __syncthreads();
+    for (int s = 1; s < kScanThreads; s <<= 1) {
+        int64_t add = t >= s ? part[t - s] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    const int64_t off = part[t] - acc;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t idx = base + q;
+        if (idx < n) d[idx] = v[q] + off;
+    }
+    if (t == kScanThreads - 1) sums[blockIdx.x] = part[t];
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ d, int64_t n, const int64_t* __restrict__ offs) {
+    const int64_t idx = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+    const int64_t o = offs[blockIdx.x];
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = idx + (int64_t)q * kScanThreads;
+        if (i < n) d[i] += o;
+    }
+}
+
+// ---------------------------------------------------- gather (a6 final)
+__global__ void k_gather(int64_t P, const int64_t* __restrict__ nnz_off, const int64_t* __restrict__ pair_base, const int32_t* __restrict__ pool_col,
+                         const float* __restrict__ pool_val, int32_t* __restrict__ col, float* __restrict__ val,
+                         int64_t cap) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p = w0; p < P; p += nw) {
+        // nnz_off is the exclusive scan of the per-pair counts (P+1 entries)
+        const int64_t dst = nnz_off[p], c = nnz_off[p + 1] - dst, src = pair_base[p];
+        if (src + c > cap || dst + c > cap) continue;  // overflowed run: reported by the host
+        for (int64_t e = lane; e < c; e += kWave) {
+            col[dst + e] = pool_col[src + e];
+            val[dst + e] = pool_val[src + e];
+        }
+    }
+}
+
+// ================================================================ host side
+hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, int fp64, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(k_tables<double>, dim3(1), dim3(256), 0, s, p, reinterpret_cast<double2*>(tab), c);
+    else
+        hipLaunchKernelGGL(k_tables<float>, dim3(1), dim3(256), 0, s, p, reinterpret_cast<float2*>(tab), c);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int* ints, int n, hipStream_t s) {
+    const int blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_reset, dim3(blocks > 1024 ? 1024 : blocks), dim3(256), 0, s, ints, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j, int64_t P,
+                        int32_t* pi, int32_t* pj, int64_t* rows1, int32_t* key, int* hist, int64_t* pair_nnz,
+                        hipStream_t s) {
+    const int64_t blocks = (P + 255) / 256;
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, n, lens, list_i, list_j,
+                       P, pi, pj, rows1, key, hist, pair_nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_bins(const int* hist, int* bin_start, hipStream_t s) {
+    hipLaunchKernelGGL(k_bins, dim3(1), dim3(kKeyBins), 0, s, hist, bin_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_queue(int64_t P, const int32_t* key, const int* bin_start, int* bin_fill, int32_t* queue,
+                             hipStream_t s) {
+    const int64_t blocks = (P + 255) / 256;
+    hipLaunchKernelGGL(k_fill_queue, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, P, key, bin_start,
+                       bin_fill, queue);
+    return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) {
+    int64_t tot = 0;
+    while (n > 1) {
+        const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+        tot += nb + 1;
+        n = nb;
+    }
+    return tot + 1;
+}
+
+hipError_t scan_i64(int64_t* d, int64_t n, int64_t* tmp, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d, n, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nb == 1) return e;
+    e = scan_i64(tmp, nb, tmp + nb + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d, n, tmp);
+    return hipGetLastError();
+}
+
+template <int RMAX>
+static hipError_t launch_pairs_r(int fp64, int grid, const PairArgs& a, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL((k_pairs<RMAX, double>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pairs<RMAX, float>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(int rmax, int fp64, int grid, const PairArgs& a, hipStream_t s) {
+    switch (rmax) {
+        case 1: return launch_pairs_r<1>(fp64, grid, a, s);
+        case 2: return launch_pairs_r<2>(fp64, grid, a, s);
+        case 3: return launch_pairs_r<3>(fp64, grid, a, s);
+        case 4: return launch_pairs_r<4>(fp64, grid, a, s);
+        case 5: return launch_pairs_r<5>(fp64, grid, a, s);
+        case 6: return launch_pairs_r<6>(fp64, grid, a, s);
+        case 7: return launch_pairs_r<7>(fp64, grid, a, s);
+        default: return launch_pairs_r<8>(fp64, grid, a, s);
+    }
+}
+
+template <int RMAX>
+static int blocks_per_cu_r(int fp64) {
+    int nb = 0;
+    hipError_t e;
+    if (fp64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs<RMAX, double>,
+                                                         kWave * kWavesPerBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs<RMAX, float>,
+                                                         kWave * kWavesPerBlock, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+int pairs_blocks_per_cu(int rmax, int fp64) {
+    switch (rmax) {
+        case 1: return blocks_per_cu_r<1>(fp64);
+        case 2: return blocks_per_cu_r<2>(fp64);
+        case 3: return blocks_per_cu_r<3>(fp64);
+        case 4: return blocks_per_cu_r<4>(fp64);
+        case 5: return blocks_per_cu_r<5>(fp64);
+        case 6: return blocks_per_cu_r<6>(fp64);
+        case 7: return blocks_per_cu_r<7>(fp64);
+        default: return blocks_per_cu_r<8>(fp64);
+    }
+}
+
+size_t fwd_bnd_bytes(int fp64) { return fp64 ? sizeof(FwdBnd<double>) : sizeof(FwdBnd<float>); }
+size_t bwd_bnd_bytes(int fp64) { return fp64 ? sizeof(BwdBnd<double>) : sizeof(BwdBnd<float>); }
+
+hipError_t launch_gather(int64_t P, const int64_t* nnz_off, const int64_t* pair_base,
+                         const int32_t* pool_col, const float* pool_val, int32_t* col, float* val, int64_t cap,
+                         hipStream_t s) {
+    int64_t blocks = (P + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, s, P, nnz_off, pair_base, pool_col,
+                       pool_val, col, val, cap);
+    return hipGetLastError();
+}
+
+}  // namespace qp

@@ -1,0 +1,94 @@
+// Internal interface between the C-ABI host code (qp_api.cpp) and the gfx950
+// kernels (qp_device.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qp {
+
+constexpr int kWave = 64;           // lanes per wavefront on CDNA
+constexpr int kWavesPerBlock = 4;   // one wave per SIMD of a CU
+constexpr int kTabW = 32;           // stride of a table row (20 y codes, padded)
+constexpr int kPadCode = 20;        // x code of rows past the end of a strip
+constexpr int kTabRows = 21;        // 20 residues + the padding row
+constexpr int kRMax = 8;            // largest rows-per-lane instantiation
+constexpr int kRescaleEvery = 8;    // steps between power-of-two rescales
+constexpr int kKeyBins = 1024;      // cost classes of the longest-first queue
+
+// Model constants in the scaled-variable form used by the kernels, computed
+// on the device from the raw parameters (k_tables).
+struct DevConsts {
+    double tau;        // M->M of the pair-HMM
+    double eps1, eps2; // gap extension per class
+    double c1, c2;     // delta_k * (1 - eps_k)
+    double u, o;       // partition function: extension and opening weights
+    double w_hmm;      // weight of the HMM posterior
+};
+
+// Raw parameters as copied to the device for k_tables.
+struct DevParams {
+    double joint[400];
+    double score[400];
+    double gap_open[2];
+    double gap_extend[2];
+    double pf_gap_open, pf_gap_extend, temperature, w_hmm;
+    int32_t n_gap_classes;
+};
+
+struct PairArgs {
+    // inputs
+    const uint8_t* seqs;
+    const int64_t* seq_off;
+    const int32_t* lens;
+    const int32_t* pair_i;
+    const int32_t* pair_j;
+    const int32_t* queue;       // pair ids in processing order
+    int64_t n_pairs;
+    int* queue_head;
+    const void* tab;            // [kTabRows * kTabW] (e_hmm, w_pf) pairs
+    const DevConsts* consts;
+    float thresh;
+    int cap;                    // staging entries per row
+    // outputs
+    const int64_t* row_off;
+    int32_t* row_ptr;
+    int64_t* pair_nnz;          // [n_pairs + 1]
+    int64_t* pair_base;         // [n_pairs]
+    int32_t* pool_col;
+    float* pool_val;
+    int64_t pool_cap;
+    unsigned long long* pool_head;
+    double* dist;
+    double* logz;
+    int* flags;                 // bit0 pool overflow, bit1 staging overflow
+    // per-wave scratch slots
+    char* scratch;
+    int64_t slot_bytes;
+    int64_t off_exps, off_fb, off_bb, off_stage_col, off_stage_val;
+    int64_t spill_band_stride;  // value pairs per band
+    int64_t exps_band_stride;   // int2 per band
+    int64_t bnd_stride;         // boundary records per buffer
+};
+
+// kernels launched by the host code (qp_device.hip)
+hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, int fp64, hipStream_t s);
+hipError_t launch_reset(int* ints, int n_ints, hipStream_t s);
+hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j,
+                        int64_t n_pairs, int32_t* pair_i, int32_t* pair_j, int64_t* rows1, int32_t* key,
+                        int* hist, int64_t* pair_nnz, hipStream_t s);
+hipError_t launch_bins(const int* hist, int* bin_start, hipStream_t s);
+hipError_t launch_fill_queue(int64_t n_pairs, const int32_t* key, const int* bin_start, int* bin_fill,
+                             int32_t* queue, hipStream_t s);
+// exclusive scan of n int64 values in place; tmp must hold scan_tmp_elems(n)
+int64_t scan_tmp_elems(int64_t n);
+hipError_t scan_i64(int64_t* data, int64_t n, int64_t* tmp, hipStream_t s);
+hipError_t launch_pairs(int rmax, int fp64, int grid, const PairArgs& a, hipStream_t s);
+int pairs_blocks_per_cu(int rmax, int fp64);
+hipError_t launch_gather(int64_t n_pairs, const int64_t* nnz_off, const int64_t* pair_base, const int32_t* pool_col, const float* pool_val,
+                         int32_t* col, float* val, int64_t cap, hipStream_t s);
+size_t fwd_bnd_bytes(int fp64);
+size_t bwd_bnd_bytes(int fp64);
+
+}  // namespace qp

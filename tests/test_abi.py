@@ -1,0 +1,119 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/qp.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1512_07437_amd import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qp_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1512_07437_amd import binding
+    return binding
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = _declared()
+    assert "qp_posteriors" in names and "qp_server_submit" in names
+    for name in names:
+        assert hasattr(B.lib, name), name
+        assert name in B.SIGNATURES, "binding lacks " + name
+
+
+def test_version(B):
+    assert B.qp_version() >> 16 == 1
+
+
+def test_struct_layout(B):
+    # qp_params: 400 doubles, int32 (+pad), 2+2 doubles, 400 doubles, 4 doubles, int32 (+pad)
+    assert ctypes.sizeof(B.qp_params) == 8 * 400 + 8 + 8 * 4 + 8 * 400 + 8 * 4 + 8
+    assert ctypes.sizeof(B.qp_result) == 4 + 4 + 8 * 3 + 8 * 9 + 8
+
+
+def _good(params):
+    from paper_1512_07437_amd import binding as B
+    return B.make_params(params)
+
+
+def test_params_check(B, params):
+    p = _good(params)
+    assert B.qp_params_check(p) == B.QP_OK
+    bad = []
+    q = _good(params); q.joint[1] += 1e-6; bad.append(q)                 # not symmetric / sum
+    q = _good(params); q.n_gap_classes = 3; bad.append(q)
+    q = _good(params); q.gap_open[0] = 0.3; q.gap_open[1] = 0.3; bad.append(q)  # tau <= 0
+    q = _good(params); q.temperature = 0.0; bad.append(q)
+    q = _good(params); q.w_hmm = 1.5; bad.append(q)
+    q = _good(params); q.precision = 7; bad.append(q)
+    q = _good(params); q.score[3] = float("nan"); bad.append(q)
+    q = _good(params); q.gap_extend[0] = 1.0; bad.append(q)
+    for q in bad:
+        assert B.qp_params_check(q) == B.QP_EINVAL
+        assert B.qp_last_error()
+
+
+def test_validation_before_device(B, params):
+    p = _good(params)
+    fam = W.c1_family()[:3]
+    with pytest.raises(B.QpError) as e:
+        B.qp_posteriors(fam[:2] + [np.zeros(0, np.uint8)], p, 0.01)
+    assert e.value.status == B.QP_EINVAL and "lens[2]" in str(e.value)
+    bad = fam[0].copy()
+    bad[5] = 20
+    with pytest.raises(B.QpError) as e:
+        B.qp_posteriors([bad, fam[1]], p, 0.01)
+    assert e.value.status == B.QP_EINVAL and "residue" in str(e.value)
+    for t in (0.0, -1.0, 1.5, float("nan")):
+        with pytest.raises(B.QpError) as e:
+            B.qp_posteriors(fam, p, t)
+        assert e.value.status == B.QP_EINVAL
+    with pytest.raises(B.QpError) as e:
+        B.qp_posteriors_pairs(fam, [0], [0], p, 0.01)
+    assert e.value.status == B.QP_EINVAL
+    with pytest.raises(B.QpError) as e:
+        B.qp_posteriors_pairs(fam, [0], [3], p, 0.01)
+    assert e.value.status == B.QP_EINVAL
+
+
+def test_empty_family_needs_no_device(B, params):
+    p = _good(params)
+    for fam in ([], W.c1_family()[:1]):
+        r = B.qp_posteriors(fam, p, 0.01)
+        assert r["n_pairs"] == 0 and r["nnz"] == 0
+        assert list(r["row_off"]) == [0] and list(r["nnz_off"]) == [0]
+    r = B.qp_posteriors_pairs(W.c1_family(), [], [], p, 0.01)
+    assert r["n_pairs"] == 0
+
+
+def _hip_devices() -> int:
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+    except OSError:
+        return 0
+    n = ctypes.c_int(0)
+    return n.value if hip.hipGetDeviceCount(ctypes.byref(n)) == 0 else 0
+
+
+def test_no_device_is_reported(B, params):
+    if _hip_devices() > 0:
+        pytest.skip("a GPU is present")
+    with pytest.raises(B.QpError) as e:
+        B.qp_posteriors(W.c1_family()[:2], _good(params), 0.01)
+    assert e.value.status == B.QP_EDEVICE
+
+
+def test_result_free_null_safe(B):
+    B.lib.qp_result_free(None)
+    B.lib.qp_plan_destroy(None)
