@@ -1,0 +1,200 @@
+"""Benchmark: all-pairs posterior matrices of one synthetic protein family.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c5]
+                [--precision fp32|fp64] [--no-graph] [--no-cpu]
+
+One step = the whole hot path on device-resident inputs: parameter tables,
+pair schedule (cost classes, longest-first queue), the fused forward /
+backward / posterior / threshold / MEA kernel, CSR compaction and the
+pair-ordered gather.  Prints one JSON line.
+
+The default workload is 200 sequences of lengths U{250..350} evolved from one
+root (19,900 pairs).  The CPU baseline times the FP64 oracle on the seeded
+200-pair sample of the same family (single thread) and the same sample gives
+the measured max |P_gpu - P_oracle|.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "all-pairs posterior GCUPS & pairs/s at ≤1e-5 vs FP64 oracle; p99 family latency"
+# algorithmic FP32 work per DP cell (both models, both passes, posterior,
+# average, MEA, threshold compare)
+FLOP_PER_CELL = 67.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def workload(name: str):
+    from paper_1512_07437_amd import workload as W
+    if name == "c1":
+        fam = W.c1_family()
+        return fam, None, "C1: 8 seqs, L~U{80..120}, 28 pairs", None
+    if name == "c2":
+        fam = W.c2_family()
+        return fam, None, "C2: 200 seqs, L~U{250..350}, 19,900 pairs", W.c2_sample()
+    if name == "c3":
+        fam = W.c3_family()
+        return fam, None, "C3: 1,000 seqs, L log-uniform [50,1500], 499,500 pairs", W.c3_sample(
+            [len(s) for s in fam])
+    if name == "c5":
+        pairs = W.c5_pairs()
+        fam = [s for ab in pairs for s in ab]
+        pi = np.arange(0, 128, 2, dtype=np.int32)
+        pj = pi + 1
+        return fam, (pi, pj), "C5: 64 divergent pairs, L~U{3000..5000}", np.arange(4)
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(fam, pairs, sample, params, res, n_seq):
+    """FP64 oracle on the sample (single thread), and the GPU error there."""
+    import oracle
+    from paper_1512_07437_amd import binding as B
+    from paper_1512_07437_amd import workload as W
+    cells = 0
+    worst = 0.0
+    ea_worst = 0.0
+    t0 = time.perf_counter()
+    for p in sample:
+        p = int(p)
+        if pairs is None:
+            i, j = W.pair_of_index(p, n_seq)
+        else:
+            i, j = int(pairs[0][p]), int(pairs[1][p])
+        r = oracle.pair(fam[i], fam[j], params, per_model=False)
+        cells += len(fam[i]) * len(fam[j])
+        rp, col, val = B.pair_csr(res, p)
+        rows = np.repeat(np.arange(len(fam[i])), np.diff(rp))
+        worst = max(worst, float(np.abs(val.astype(np.float64) - r["post"][rows, col]).max(initial=0.0)))
+        ea_worst = max(ea_worst, abs((1.0 - res["dist"][p]) - r["ea"]))
+    dt = time.perf_counter() - t0
+    return cells, dt, worst, ea_worst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--thresh", type=float, default=0.01)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the run, copy this many MiB device-to-device (a known-size kernel that "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the posterior engine runs one process on one MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    def say(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    import torch
+
+    say("torch %s imported" % torch.__version__)
+    from paper_1512_07437_amd import binding as B
+    from paper_1512_07437_amd import workload as W
+
+    fam, pairs, desc, sample = workload(args.workload)
+    mp = W.make_params(0)
+    prec = B.QP_FP64 if args.precision == "fp64" else B.QP_FP32_SCALED
+    params = B.make_params(mp, prec)
+    lens = np.array([len(s) for s in fam], dtype=np.int32)
+    if pairs is None:
+        ii, jj = np.triu_indices(len(fam), 1)
+    else:
+        ii, jj = pairs
+    cells = int(np.sum(lens[ii].astype(np.int64) * lens[jj]))
+    n_pairs = len(ii)
+
+    dev = torch.device("cuda:0")
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        say("calibration copy of %d MiB done" % args.calib_copy_mb)
+    d_seqs, d_off = B.device_inputs(fam, "cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    plan = B.Plan(lens, params, args.thresh, None if pairs is None else pairs[0],
+                  None if pairs is None else pairs[1])
+    plan.set_graph(not args.no_graph)
+    say("plan: %d pairs, %d cells, %.1f MB device" % (n_pairs, cells, plan.device_bytes() / 1e6))
+    sp = stream.cuda_stream
+    # first run sizes the sparse output exactly (grows once if needed)
+    plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+    if plan.sync_status() == B.QP_ENOSPC:
+        plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+        plan.sync()
+    for _ in range(args.warmup):
+        plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+    torch.cuda.synchronize()
+    say("warmup done")
+    plan.timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernel_ms, pipe_ms, n_timed = plan.timing()
+    plan.sync()
+    res = plan.download()
+    say("timed %d steps: %.3f ms/step" % (args.steps, dt * 1e3 / args.steps))
+
+    ms_per_step = dt * 1e3 / args.steps
+    gcups = cells / (dt / args.steps) / 1e9
+    peak = FP64_VALU_PEAK_TFLOPS if prec == B.QP_FP64 else FP32_VALU_PEAK_TFLOPS
+    achieved = cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12 if kernel_ms > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": round(gcups, 3),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32" if prec == 0 else "fp64",
+        "data": "synthetic",
+        "config": {"workload": desc, "pairs": n_pairs, "cells": cells, "thresh": args.thresh,
+                   "graph": not args.no_graph, "nnz": int(res["nnz"])},
+        "pairs_per_s": round(n_pairs / (dt / args.steps), 1),
+        "kernel_ms": round(kernel_ms, 4),
+        "pipeline_ms": round(pipe_ms, 4),
+        "roofline": {"bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
+                     "peak": peak, "unit": "TFLOP/s",
+                     "frac": None if achieved is None else round(achieved / peak, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu and sample is not None:
+        c_cells, c_dt, worst, ea_worst = cpu_baseline(fam, pairs, sample, mp, res, len(fam))
+        say("cpu baseline: %d pairs in %.1f s" % (len(sample), c_dt))
+        out["cpu_baseline"] = {"value": round(c_cells / c_dt / 1e9, 6), "unit": "GCUPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d seeded pairs of the same family (%d cells, %.1f s)" % (
+                                   len(sample), c_cells, c_dt)}
+        out["max_abs_err_vs_oracle"] = worst
+        out["max_abs_ea_err_vs_oracle"] = ea_worst
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,6 +105,7 @@ struct qp_plan {
     int64_t device_bytes = 0;
     qp::DevParams* d_params = nullptr;
     void* d_tab = nullptr;
+    void* d_col0 = nullptr;
     qp::DevConsts* d_consts = nullptr;
     int32_t* d_lens = nullptr;
     int32_t* d_list_i = nullptr;
@@ -215,6 +216,11 @@ static qp_status plan_alloc_all(qp_plan* pl) {
         ALLOC(t, (int64_t)qp::kTabRows * qp::kTabW * (pl->fp64 ? 16 : 8));
         pl->d_tab = t;
     }
+    {
+        char* t = nullptr;
+        ALLOC(t, (int64_t)pl->mmax * (int64_t)qp::col0_bytes() + 64);
+        pl->d_col0 = t;
+    }
     ALLOC(pl->d_consts, 1);
     ALLOC(pl->d_lens, pl->n);
     if (!pl->all_pairs) {
@@ -268,6 +274,7 @@ static qp_status plan_alloc_all(qp_plan* pl) {
     a.n_pairs = P;
     a.queue_head = pl->d_ints;
     a.tab = pl->d_tab;
+    a.col0 = pl->d_col0;
     a.consts = pl->d_consts;
     a.thresh = pl->thresh;
     a.cap = pl->cap;
@@ -286,24 +293,30 @@ static qp_status plan_alloc_all(qp_plan* pl) {
     return QP_OK;
 }
 
-// enqueue every step of the pipeline on s (eager); events optional
-static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, hipEvent_t* ev) {
+// record a timing event; inside a graph capture it must be an external
+// event node, otherwise it only orders the capture
+static hipError_t record(hipEvent_t e, hipStream_t s, bool capturing) {
+    return capturing ? hipEventRecordWithFlags(e, s, hipEventRecordExternal) : hipEventRecord(e, s);
+}
+
+// enqueue every step of the pipeline on s; events optional
+static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, hipEvent_t* ev, bool capturing = false) {
     const int64_t P = pl->P;
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    if (ev) HIP_TRY(record(ev[0], s, capturing));
     HIP_TRY(qp::launch_reset(pl->d_ints, pl->n_ints, s));
-    HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->fp64, s));
+    HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->d_col0, pl->mmax, pl->fp64, s));
     HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
                              pl->d_key, pl->d_ints + 2, pl->d_nnz, s));
     HIP_TRY(qp::launch_bins(pl->d_ints + 2, pl->d_bin_start, s));
     HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + 2 + qp::kKeyBins, pl->d_queue, s));
     HIP_TRY(qp::scan_i64(pl->d_rowoff, P + 1, pl->d_scan_tmp, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (ev) HIP_TRY(record(ev[1], s, capturing));
     HIP_TRY(qp::launch_pairs(pl->rmax, pl->fp64, pl->grid, pl->args, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    if (ev) HIP_TRY(record(ev[2], s, capturing));
     HIP_TRY(qp::scan_i64(pl->d_nnz, P + 1, pl->d_scan_tmp, s));
     HIP_TRY(qp::launch_gather(P, pl->d_nnz, pl->d_base, pl->d_pool_col, pl->d_pool_val, pl->d_col,
                               pl->d_val, pl->pool_cap, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    if (ev) HIP_TRY(record(ev[3], s, capturing));
     return QP_OK;
 }
 
@@ -318,7 +331,7 @@ static qp_status capture_graphs(qp_plan* pl) {
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return fail(QP_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
-        qp_status st = enqueue_pipeline(pl, pl->cap_stream, pl->ev[g]);
+        qp_status st = enqueue_pipeline(pl, pl->cap_stream, pl->ev[g], true);
         e = hipStreamEndCapture(pl->cap_stream, &graph);
         if (st != QP_OK) {
             if (graph) hipGraphDestroy(graph);

@@ -26,6 +26,7 @@
 // threshold, the per-row staging of CSR entries and the reverse MEA recursion.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
 
@@ -51,6 +52,12 @@ template <typename T> struct BwdBnd {
 
 template <typename T> struct Coef {
     T tau, eps1, eps2, c1, c2, u, o;
+};
+
+// D(i,0) of both models for row i (1-based, index i-1): mantissa and exponent
+struct Col0 {
+    double mH, mP;
+    int eH, eP;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -102,11 +109,10 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 
 // ---------------------------------------------------------------- forward
 // One band of rows [r0, r0+rows) of pair (x, y); L lanes carry R rows each.
-template <int R, typename T>
+template <int R, typename T, bool first, bool last>
 __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* __restrict__ y, int n, int r0,
-                         int rows, int L, bool first, bool last, const typename Pair2<T>::type* tab,
-                         const Coef<T>& k, const double lg_eps1, const double lg_eps2, const double lg_u,
-                         const double lg_c1, const double lg_c2, const double lg_o,
+                         int rows, int L, const typename Pair2<T>::type* tab,
+                         const Coef<T>& k, const Col0* __restrict__ col0,
                          typename Pair2<T>::type* __restrict__ spill, int2* __restrict__ exps,
                          const FwdBnd<T>* __restrict__ fin, FwdBnd<T>* __restrict__ fout, T& zH, T& zP,
                          int& ezH, int& ezP) {
@@ -118,40 +124,45 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         int row = lane * R + r;
         xo[r] = (used && row < rows ? (int)x[r0 + row] : kPadCode) * kTabW;
     }
-    // carried per row: M, V1, V2 (horizontal), D (into-M sum for the diagonal)
-    T M[R], V1[R], V2r[R], D[R], gM[R], gV[R], gD[R];
+    // carried per row: W_k = V_k at the lane's next column (horizontal gap
+    // runs, already extended by this column's match), D = into-M sum of the
+    // current column (the diagonal input of the row below); PF alike
+    T W1[R], W2[R], D[R], gW[R], gD[R];
     int EH, EP;
     {
-        // column 0: only vertical gap runs from the virtual begin state
-        // U_k(i,0) = eps_k^(i-1), D(i,0) = c1 U1 + c2 U2; PF alike with u, o
-        double lgH = -INFINITY, lgP = -INFINITY;
+        // column 0: only vertical gap runs from the virtual begin state,
+        // D(i,0) = sum_k c_k eps_k^(i-1) (PF: o u^(i-1)), tabulated per row
+        Col0 c0[R];
+        EH = INT_MIN;
+        EP = INT_MIN;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            int i0 = r0 + lane * R + r;  // = i - 1
-            double a1 = (i0 == 0 ? 0.0 : (double)i0 * lg_eps1) + lg_c1;
-            double a2 = (i0 == 0 ? 0.0 : (double)i0 * lg_eps2) + lg_c2;
-            double ap = (i0 == 0 ? 0.0 : (double)i0 * lg_u) + lg_o;
-            lgH = fmax(lgH, fmax(a1, a2));
-            lgP = fmax(lgP, ap);
+            const int row = lane * R + r;  // rows past the band are padding: zero
+            if (used && row < rows) {
+                c0[r] = col0[r0 + row];
+            } else {
+                c0[r].mH = 0.0;
+                c0[r].mP = 0.0;
+                c0[r].eH = 0;
+                c0[r].eP = 0;
+            }
+            EH = max(EH, c0[r].mH != 0.0 ? c0[r].eH : INT_MIN);
+            EP = max(EP, c0[r].mP != 0.0 ? c0[r].eP : INT_MIN);
         }
-        EH = isfinite(lgH) ? (int)floor(lgH) : 0;
-        EP = isfinite(lgP) ? (int)floor(lgP) : 0;
+        if (EH == INT_MIN) EH = 0;
+        if (EP == INT_MIN) EP = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            int i0 = r0 + lane * R + r;
-            double u1 = pow2s(lg_eps1, i0, EH), u2 = pow2s(lg_eps2, i0, EH), gu = pow2s(lg_u, i0, EP);
-            M[r] = T(0);
-            V1[r] = T(0);
-            V2r[r] = T(0);
-            gM[r] = T(0);
-            gV[r] = T(0);
-            D[r] = (T)((double)k.c1 * u1 + (double)k.c2 * u2);
-            gD[r] = (T)((double)k.o * gu);
+            W1[r] = T(0);  // V_k(i,1) = M(i,0) + eps V_k(i,0) = 0
+            W2[r] = T(0);
+            gW[r] = T(0);
+            D[r] = qldexp((T)c0[r].mH, c0[r].eH - EH);
+            gD[r] = qldexp((T)c0[r].mP, c0[r].eP - EP);
         }
     }
-    // what this lane hands to the lane below: its last row at its current column
-    T oM = T(0), oU1 = T(0), oU2 = T(0), oD = D[R - 1], ogM = T(0), ogU = T(0), ogD = gD[R - 1];
-    int oEH = EH, oEP = EP;
+    // vertical values of the strip's last row at the lane's current column,
+    // handed to the lane below together with D[R-1], gD[R-1] and EH, EP
+    T oM = T(0), oU1 = T(0), oU2 = T(0), ogM = T(0), ogU = T(0);
     // diagonal input of the strip's first row (row above, previous column)
     T aD = T(0), gaD = T(0);
     // virtual row 0 (first band, lane 0): V_k(0,j) = eps_k^(j-1), j >= 1
@@ -164,7 +175,7 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             tv2 = tv1;
             tgv = qldexp(T(1), -EP);
         } else {
-            FwdBnd<T> b = fin[0];
+            const FwdBnd<T> b = fin[0];
             aD = qldexp(b.D, b.EH - EH);
             gaD = qldexp(b.gD, b.EP - EP);
         }
@@ -180,19 +191,17 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     const int S = n + L - 1;
     int jn = 1 - lane;  // column of step 0
     int ycur = (used && jn >= 1 && jn <= n) ? (int)y[jn - 1] : 0;
-    FwdBnd<T> bnext;
-    if (!first && lane == 0) bnext = fin[1 <= n ? 1 : n];
+    FwdBnd<T> bq;  // lane 0 of a lower band: boundary record of its next column
+    if (!first && lane == 0) bq = fin[1];
     for (int s = 0; s < S; ++s) {
         const int j = s - lane + 1;
         const bool active = used && j >= 1 && j <= n;
-        int ynext = (used && j + 1 >= 1 && j + 1 <= n) ? (int)y[j] : 0;
-        FwdBnd<T> bcur = bnext;
-        if (!first && lane == 0) bnext = fin[s + 2 <= n ? s + 2 : n];
+        const int ynext = (int)y[min(max(j, 0), n - 1)];  // clamped: read only when in range
         // ---- exchange with the lane above
         T rM = dpp<kDppWaveShr1>(oM), rU1 = dpp<kDppWaveShr1>(oU1), rU2 = dpp<kDppWaveShr1>(oU2);
-        T rD = dpp<kDppWaveShr1>(oD), rgM = dpp<kDppWaveShr1>(ogM), rgU = dpp<kDppWaveShr1>(ogU);
-        T rgD = dpp<kDppWaveShr1>(ogD);
-        int rEH = dpp_i<kDppWaveShr1>(oEH), rEP = dpp_i<kDppWaveShr1>(oEP);
+        T rD = dpp<kDppWaveShr1>(D[R - 1]), rgM = dpp<kDppWaveShr1>(ogM), rgU = dpp<kDppWaveShr1>(ogU);
+        T rgD = dpp<kDppWaveShr1>(gD[R - 1]);
+        int rEH = dpp_i<kDppWaveShr1>(EH), rEP = dpp_i<kDppWaveShr1>(EP);
         if (lane == 0) {
             if (first) {
                 rM = T(0); rU1 = T(0); rU2 = T(0);
@@ -202,9 +211,10 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 rEH = EH; rEP = EP;
                 tv1 *= k.eps1; tv2 *= k.eps2; tgv *= k.u;
             } else {
-                rM = bcur.M; rU1 = bcur.U1; rU2 = bcur.U2; rD = bcur.D;
-                rgM = bcur.gM; rgU = bcur.gU; rgD = bcur.gD;
-                rEH = bcur.EH; rEP = bcur.EP;
+                rM = bq.M; rU1 = bq.U1; rU2 = bq.U2; rD = bq.D;
+                rgM = bq.gM; rgU = bq.gU; rgD = bq.gD;
+                rEH = bq.EH; rEP = bq.EP;
+                bq = fin[s + 2 <= n ? s + 2 : n];
             }
         }
         {
@@ -215,38 +225,38 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         if (active) {
             T upM = rM, upU1 = rU1, upU2 = rU2, dg = aD;
             T gupM = rgM, gupU = rgU, gdg = gaD;
-            V2* sp = spill + (int64_t)s * R * kWave + lane;
+            V2* sp = spill + (int64_t)s * R * kWave;  // uniform step base
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const V2 e = tab[xo[r] + ycur];
                 const T nM = e.x * dg;
                 const T nU1 = fma(k.eps1, upU1, upM);
                 const T nU2 = fma(k.eps2, upU2, upM);
-                const T nV1 = fma(k.eps1, V1[r], M[r]);
-                const T nV2 = fma(k.eps2, V2r[r], M[r]);
-                const T nD = fma(k.c2, nU2 + nV2, fma(k.c1, nU1 + nV1, k.tau * nM));
+                const T nD = fma(k.c2, nU2 + W2[r], fma(k.c1, nU1 + W1[r], k.tau * nM));
                 const T ngM = e.y * gdg;
                 const T ngU = fma(k.u, gupU, gupM);
-                const T ngV = fma(k.u, gV[r], gM[r]);
-                const T ngD = fma(k.o, ngU + ngV, ngM);
+                const T ngD = fma(k.o, ngU + gW[r], ngM);
+                W1[r] = fma(k.eps1, W1[r], nM);
+                W2[r] = fma(k.eps2, W2[r], nM);
+                gW[r] = fma(k.u, gW[r], ngM);
                 dg = D[r];
                 gdg = gD[r];
-                M[r] = nM; V1[r] = nV1; V2r[r] = nV2; D[r] = nD;
-                gM[r] = ngM; gV[r] = ngV; gD[r] = ngD;
+                D[r] = nD;
+                gD[r] = ngD;
                 upM = nM; upU1 = nU1; upU2 = nU2;
                 gupM = ngM; gupU = ngU;
                 V2 st;
                 st.x = nM;
                 st.y = ngM;
-                sp[r * kWave] = st;
+                sp[r * kWave + lane] = st;
             }
-            exps[(int64_t)s * kWave + lane] = make_int2(EH, EP);
-            oM = upM; oU1 = upU1; oU2 = upU2; oD = D[R - 1];
-            ogM = gupM; ogU = gupU; ogD = gD[R - 1];
+            (exps + (int64_t)s * kWave)[lane] = make_int2(EH, EP);
+            oM = upM; oU1 = upU1; oU2 = upU2;
+            ogM = gupM; ogU = gupU;
             if (!last && lane == L - 1) {
                 FwdBnd<T> b;
-                b.M = oM; b.U1 = oU1; b.U2 = oU2; b.D = oD;
-                b.gM = ogM; b.gU = ogU; b.gD = ogD;
+                b.M = oM; b.U1 = oU1; b.U2 = oU2; b.D = D[R - 1];
+                b.gM = ogM; b.gU = ogU; b.gD = gD[R - 1];
                 b.EH = EH; b.EP = EP;
                 fout[j] = b;
             }
@@ -264,19 +274,16 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             const int sh = -qexp(mh), sp = -qexp(mp);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                M[r] = qldexp(M[r], sh); V1[r] = qldexp(V1[r], sh); V2r[r] = qldexp(V2r[r], sh);
-                D[r] = qldexp(D[r], sh);
-                gM[r] = qldexp(gM[r], sp); gV[r] = qldexp(gV[r], sp); gD[r] = qldexp(gD[r], sp);
+                W1[r] = qldexp(W1[r], sh); W2[r] = qldexp(W2[r], sh); D[r] = qldexp(D[r], sh);
+                gW[r] = qldexp(gW[r], sp); gD[r] = qldexp(gD[r], sp);
             }
-            oM = qldexp(oM, sh); oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh); oD = qldexp(oD, sh);
+            oM = qldexp(oM, sh); oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh);
             aD = qldexp(aD, sh); tv1 = qldexp(tv1, sh); tv2 = qldexp(tv2, sh);
-            ogM = qldexp(ogM, sp); ogU = qldexp(ogU, sp); ogD = qldexp(ogD, sp);
+            ogM = qldexp(ogM, sp); ogU = qldexp(ogU, sp);
             gaD = qldexp(gaD, sp); tgv = qldexp(tgv, sp);
             EH -= sh;
             EP -= sp;
         }
-        oEH = EH;
-        oEP = EP;
     }
     if (last) {
         // Z = D(m, n): last real row of the band, held by lane L-1
@@ -293,14 +300,16 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
 }
 
 // --------------------------------------------------------------- backward
-template <int R, typename T>
+// FIRST / LAST: the band is the top / bottom band of the pair (compile time,
+// so single-band pairs carry no band-boundary code).
+template <int R, typename T, bool FIRST, bool LAST>
 __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* __restrict__ y, int n, int r0,
-                         int rows, int L, bool first, bool last, const typename Pair2<T>::type* tab,
-                         const Coef<T>& k, const typename Pair2<T>::type* __restrict__ spill,
-                         const int2* __restrict__ exps, const BwdBnd<T>* __restrict__ bin,
-                         BwdBnd<T>* __restrict__ bout, T invZH, T invZP, int ezH, int ezP, float thresh,
-                         int cap, int32_t* __restrict__ stage_col, float* __restrict__ stage_val,
-                         int32_t* __restrict__ rowcnt, int* __restrict__ flags, double& a11) {
+                         int rows, int L, const typename Pair2<T>::type* tab, const Coef<T>& k,
+                         const typename Pair2<T>::type* __restrict__ spill, const int2* __restrict__ exps,
+                         const BwdBnd<T>* __restrict__ bin, BwdBnd<T>* __restrict__ bout, T invZH, T invZP, int ezH,
+                         int ezP, float thresh, int cap, int32_t* __restrict__ stage_col,
+                         float* __restrict__ stage_val, int32_t* __restrict__ rowcnt, int* __restrict__ flags,
+                         double& a11) {
     using V2 = typename Pair2<T>::type;
     const bool used = lane < L;
     int xo[R];
@@ -324,7 +333,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     // diagonal input of the strip's last row (row below, next column)
     T bT = T(0), bgT = T(0);
     double bA = 0.0;
-    if (last && lane == L - 1) {
+    if (LAST && lane == L - 1) {
         // end state: the cell after (m, n) contributes weight 1 to (m, n)
         const int rm = (rows - 1) - (L - 1) * R;
 #pragma unroll
@@ -332,59 +341,75 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             if (r == rm + 1) { Tp[r] = T(1); gTp[r] = T(1); }
         if (rm + 1 == R) { bT = T(1); bgT = T(1); }
     }
-    T oU1 = T(0), oU2 = T(0), oT = T(0), ogU = T(0), ogT = T(0);
-    double oA = 0.0;
-    int oFH = 0, oFP = 0;
+    // vertical values of the strip's first row at the lane's current column,
+    // handed to the lane above together with Tp[0], gTp[0], A[0] and FH, FP
+    T oU1 = T(0), oU2 = T(0), ogU = T(0);
 
     const int S = n + L - 1;
-    const int lead = L - 1 - lane;
-    auto col_of = [&](int t) { return n - t + lead; };
-    int jc = col_of(0);
-    int ycur = (used && jc >= 1 && jc <= n) ? (int)y[jc - 1] : 0;
-    V2 fcur[R], fnext[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) { fnext[r].x = T(0); fnext[r].y = T(0); }
-    int2 ecur = make_int2(0, 0), enext = make_int2(0, 0);
-    if (used && jc >= 1 && jc <= n) {
-        const V2* sp = spill + (int64_t)(S - 1) * R * kWave + lane;
-#pragma unroll
-        for (int r = 0; r < R; ++r) fcur[r] = sp[r * kWave];
-        ecur = exps[(int64_t)(S - 1) * kWave + lane];
-    } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) { fcur[r].x = T(0); fcur[r].y = T(0); }
+    const int lead = L - 1 - lane;  // lane L-1 starts at column n
+    int ycur;
+    {
+        const int j0 = n + lead;
+        ycur = (used && j0 <= n) ? (int)y[j0 - 1] : 0;
     }
-    BwdBnd<T> bnext;
-    if (!last && lane == L - 1) bnext = bin[n];
-    for (int t = 0; t < S; ++t) {
-        const int j = col_of(t);
-        const bool active = used && j >= 1 && j <= n;
-        const bool nact = used && j - 1 >= 1 && j - 1 <= n;
-        // prefetch the next step's residue, forward values and boundary
-        int ynext = nact ? (int)y[j - 2] : 0;
-        if (nact) {
-            const V2* sp = spill + (int64_t)(S - 2 - t) * R * kWave + lane;
+    V2 fa[R], fb[R];
+    int2 ea = make_int2(0, 0), eb = make_int2(0, 0);
 #pragma unroll
-            for (int r = 0; r < R; ++r) fnext[r] = sp[r * kWave];
-            enext = exps[(int64_t)(S - 2 - t) * kWave + lane];
+    for (int r = 0; r < R; ++r) {
+        fa[r].x = T(0); fa[r].y = T(0); fb[r].x = T(0); fb[r].y = T(0);
+    }
+    if (used && lead == 0) {
+        const V2* sp = spill + (int64_t)(S - 1) * R * kWave;
+#pragma unroll
+        for (int r = 0; r < R; ++r) fa[r] = sp[r * kWave + lane];
+        ea = (exps + (int64_t)(S - 1) * kWave)[lane];
+    }
+    BwdBnd<T> bq;  // lane L-1 of an upper band: boundary record of its next column
+    if (!LAST && lane == L - 1) bq = bin[n];
+
+    // one step: uses the forward values in fc/ec, prefetches the next step's
+    // into fn/en
+    auto step = [&](const int t, const V2 (&fc)[R], const int2 ec, V2 (&fn)[R], int2& en) {
+        const int j = n - t + lead;
+        const bool active = used && j >= 1 && j <= n;
+        // prefetch the next step unconditionally (clamped in range), so the
+        // loads are straight-line and the wait for them is counted exactly;
+        // lanes outside their columns never read what they loaded
+        const int tn = t + 1 < S ? S - 2 - t : 0;
+        const int yi = min(max(j - 2, 0), n - 1);
+        const int ynext = (int)y[yi];
+        {
+            const V2* sp = spill + (int64_t)tn * R * kWave;
+#pragma unroll
+            for (int r = 0; r < R; ++r) fn[r] = sp[r * kWave + lane];
+            en = (exps + (int64_t)tn * kWave)[lane];
         }
-        BwdBnd<T> bcur = bnext;
-        if (!last && lane == L - 1) bnext = bin[j - 1 >= 1 ? j - 1 : 1];
         // ---- exchange with the lane below
-        T rU1 = dpp<kDppWaveShl1>(oU1), rU2 = dpp<kDppWaveShl1>(oU2), rT = dpp<kDppWaveShl1>(oT);
-        T rgU = dpp<kDppWaveShl1>(ogU), rgT = dpp<kDppWaveShl1>(ogT);
-        double rA = dpp<kDppWaveShl1>(oA);
-        int rFH = dpp_i<kDppWaveShl1>(oFH), rFP = dpp_i<kDppWaveShl1>(oFP);
-        if (lane == L - 1) {
-            if (last) {
-                rU1 = T(0); rU2 = T(0); rT = T(0); rgU = T(0); rgT = T(0);
-                rA = 0.0;
-                rFH = FH; rFP = FP;
-            } else {
-                rU1 = bcur.U1; rU2 = bcur.U2; rT = bcur.Tt; rgU = bcur.gU; rgT = bcur.gT;
-                rA = bcur.A;
-                rFH = bcur.FH; rFP = bcur.FP;
-            }
+        T rU1 = dpp<kDppWaveShl1>(oU1), rU2 = dpp<kDppWaveShl1>(oU2), rT = dpp<kDppWaveShl1>(Tp[0]);
+        T rgU = dpp<kDppWaveShl1>(ogU), rgT = dpp<kDppWaveShl1>(gTp[0]);
+        double rA = dpp<kDppWaveShl1>(A[0]);
+        int rFH = dpp_i<kDppWaveShl1>(FH), rFP = dpp_i<kDppWaveShl1>(FP);
+        const bool edge = lane == L - 1;
+        if (LAST) {
+            // below the last row: nothing (the end state entered via bT/Tp)
+            rU1 = edge ? T(0) : rU1;
+            rU2 = edge ? T(0) : rU2;
+            rT = edge ? T(0) : rT;
+            rgU = edge ? T(0) : rgU;
+            rgT = edge ? T(0) : rgT;
+            rA = edge ? 0.0 : rA;
+            rFH = edge ? FH : rFH;
+            rFP = edge ? FP : rFP;
+        } else {
+            rU1 = edge ? bq.U1 : rU1;
+            rU2 = edge ? bq.U2 : rU2;
+            rT = edge ? bq.Tt : rT;
+            rgU = edge ? bq.gU : rgU;
+            rgT = edge ? bq.gT : rgT;
+            rA = edge ? bq.A : rA;
+            rFH = edge ? bq.FH : rFH;
+            rFP = edge ? bq.FP : rFP;
+            if (edge) bq = bin[j - 1 >= 1 ? j - 1 : 1];
         }
         {
             const int dH = rFH - FH, dP = rFP - FP;
@@ -396,7 +421,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             double dA = rA;
             T dgT = bT, dggT = bgT;
             double dgA = bA;
-            const int kH = ecur.x + FH - ezH, kP = ecur.y + FP - ezP;
+            const int kH = ec.x + FH - ezH, kP = ec.y + FP - ezP;
 #pragma unroll
             for (int r = R - 1; r >= 0; --r) {
                 const V2 e = tab[xo[r] + ycur];
@@ -411,15 +436,15 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 const T ngV = fma(k.u, gbV[r], tg);
                 const T gbM = fma(k.o, dgU + gbV[r], tg);
                 const T ngT = e.y * gbM;
-                const T pH = qldexp(fcur[r].x * bM * invZH, kH);
-                const T pP = qldexp(fcur[r].y * gbM * invZP, kP);
+                const T pH = qldexp(fc[r].x * bM * invZH, kH);
+                const T pP = qldexp(fc[r].y * gbM * invZP, kP);
                 const T P = pH + pP;
                 const double nA = fmax(dgA + (double)P, fmax(dA, A[r]));
                 const int row = lane * R + r;
                 if (P >= (T)thresh && row < rows) {
                     const int c = cnt[r];
                     if (c < cap) {
-                        const int64_t at = (int64_t)(r0 + row) * cap + c;
+                        const uint32_t at = (uint32_t)(r0 + row) * (uint32_t)cap + (uint32_t)c;
                         stage_col[at] = j - 1;
                         stage_val[at] = (float)P;
                     }
@@ -430,10 +455,10 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 bV1[r] = nV1; bV2[r] = nV2; gbV[r] = ngV;
                 dU1 = nU1; dU2 = nU2; dgU = ngU; dA = nA;
             }
-            oU1 = dU1; oU2 = dU2; oT = Tp[0]; ogU = dgU; ogT = gTp[0]; oA = A[0];
-            if (!first && lane == 0) {
+            oU1 = dU1; oU2 = dU2; ogU = dgU;
+            if (!FIRST && lane == 0) {
                 BwdBnd<T> b;
-                b.U1 = oU1; b.U2 = oU2; b.Tt = oT; b.gU = ogU; b.gT = ogT; b.A = oA;
+                b.U1 = oU1; b.U2 = oU2; b.Tt = Tp[0]; b.gU = ogU; b.gT = gTp[0]; b.A = A[0];
                 b.FH = FH; b.FP = FP;
                 bout[j] = b;
             }
@@ -442,9 +467,6 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         bgT = rgT;
         bA = rA;
         ycur = ynext;
-#pragma unroll
-        for (int r = 0; r < R; ++r) fcur[r] = fnext[r];
-        ecur = enext;
         if ((t % kRescaleEvery) == kRescaleEvery - 1) {
             T mh = T(0), mp = T(0);
 #pragma unroll
@@ -458,13 +480,15 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 bV1[r] = qldexp(bV1[r], sh); bV2[r] = qldexp(bV2[r], sh); Tp[r] = qldexp(Tp[r], sh);
                 gbV[r] = qldexp(gbV[r], sp); gTp[r] = qldexp(gTp[r], sp);
             }
-            oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh); oT = qldexp(oT, sh); bT = qldexp(bT, sh);
-            ogU = qldexp(ogU, sp); ogT = qldexp(ogT, sp); bgT = qldexp(bgT, sp);
+            oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh); bT = qldexp(bT, sh);
+            ogU = qldexp(ogU, sp); bgT = qldexp(bgT, sp);
             FH -= sh;
             FP -= sp;
         }
-        oFH = FH;
-        oFP = FP;
+    };
+    for (int t = 0; t < S; t += 2) {
+        step(t, fa, ea, fb, eb);
+        if (t + 1 < S) step(t + 1, fb, eb, fa, ea);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -478,16 +502,18 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             rowcnt[r0 + row] = c;
         }
     }
-    if (first) a11 = rdlane(A[0], 0);
+    if (FIRST) a11 = rdlane(A[0], 0);
 }
 
 // ------------------------------------------------------------ one pair
 template <int R, typename T>
 __device__ void process_pair(const PairArgs& a, int lane, char* slot, const typename Pair2<T>::type* tab,
-                             const Coef<T>& k, const double* lgs, int64_t p) {
+                             const Coef<T>& k, int64_t p) {
     using V2 = typename Pair2<T>::type;
-    const int pi = a.pair_i[p], pj = a.pair_j[p];
-    const int m = a.lens[pi], n = a.lens[pj];
+    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
+    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
+    const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
+    const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
     const uint8_t* x = a.seqs + a.seq_off[pi];
     const uint8_t* y = a.seqs + a.seq_off[pj];
     const int H = kWave * R;
@@ -501,14 +527,23 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
 
     T zH = T(1), zP = T(1);
     int ezH = 0, ezP = 0;
+    const Col0* col0 = reinterpret_cast<const Col0*>(a.col0);
     for (int b = 0; b < nb; ++b) {
         const int r0 = b * H;
         const int rows = min(H, m - r0);
         const int L = (rows + R - 1) / R;
-        fwd_band<R, T>(lane, x, y, n, r0, rows, L, b == 0, b == nb - 1, tab, k, lgs[0], lgs[1], lgs[2], lgs[3],
-                       lgs[4], lgs[5], spill + (int64_t)b * a.spill_band_stride,
-                       exps + (int64_t)b * a.exps_band_stride, fb + (int64_t)((b + 1) & 1) * a.bnd_stride,
-                       fb + (int64_t)(b & 1) * a.bnd_stride, zH, zP, ezH, ezP);
+        V2* sp = spill + (int64_t)b * a.spill_band_stride;
+        int2* ex = exps + (int64_t)b * a.exps_band_stride;
+        const FwdBnd<T>* fi = fb + (int64_t)((b + 1) & 1) * a.bnd_stride;
+        FwdBnd<T>* fo = fb + (int64_t)(b & 1) * a.bnd_stride;
+        if (nb == 1)
+            fwd_band<R, T, true, true>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
+        else if (b == 0)
+            fwd_band<R, T, true, false>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
+        else if (b == nb - 1)
+            fwd_band<R, T, false, true>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
+        else
+            fwd_band<R, T, false, false>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
         __threadfence_block();
     }
     const T invZH = T(a.consts->w_hmm) / zH;
@@ -519,10 +554,22 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
         const int r0 = b * H;
         const int rows = min(H, m - r0);
         const int L = (rows + R - 1) / R;
-        bwd_band<R, T>(lane, x, y, n, r0, rows, L, b == 0, b == nb - 1, tab, k,
-                       spill + (int64_t)b * a.spill_band_stride, exps + (int64_t)b * a.exps_band_stride,
-                       bb + (int64_t)((b + 1) & 1) * a.bnd_stride, bb + (int64_t)(b & 1) * a.bnd_stride, invZH,
-                       invZP, ezH, ezP, a.thresh, a.cap, stage_col, stage_val, rp + 1, a.flags, a11);
+        const V2* sp = spill + (int64_t)b * a.spill_band_stride;
+        const int2* ex = exps + (int64_t)b * a.exps_band_stride;
+        const BwdBnd<T>* bi = bb + (int64_t)((b + 1) & 1) * a.bnd_stride;
+        BwdBnd<T>* bo = bb + (int64_t)(b & 1) * a.bnd_stride;
+#define QP_BWD(F, Lb)                                                                                      \
+    bwd_band<R, T, F, Lb>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH, ezP, a.thresh, \
+                          a.cap, stage_col, stage_val, rp + 1, a.flags, a11)
+        if (nb == 1)
+            QP_BWD(true, true);
+        else if (b == 0)
+            QP_BWD(true, false);
+        else if (b == nb - 1)
+            QP_BWD(false, true);
+        else
+            QP_BWD(false, false);
+#undef QP_BWD
         __threadfence_block();
     }
     // ---- row counts -> row pointers (inclusive scan in place)
@@ -568,15 +615,14 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
 
 template <int RR, int RMAX, typename T>
 __device__ __forceinline__ void dispatch(int R, const PairArgs& a, int lane, char* slot,
-                                         const typename Pair2<T>::type* tab, const Coef<T>& k, const double* lgs,
-                                         int64_t p) {
+                                         const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p) {
     if constexpr (RR > RMAX) {
         return;
     } else {
         if (R == RR)
-            process_pair<RR, T>(a, lane, slot, tab, k, lgs, p);
+            process_pair<RR, T>(a, lane, slot, tab, k, p);
         else
-            dispatch<RR + 1, RMAX, T>(R, a, lane, slot, tab, k, lgs, p);
+            dispatch<RR + 1, RMAX, T>(R, a, lane, slot, tab, k, p);
     }
 }
 
@@ -588,34 +634,71 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
     for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    // wave index is uniform: keep the slot pointer (and all pointers derived
+    // from it) in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     char* slot = a.scratch + (int64_t)wid * a.slot_bytes;
     const DevConsts c = *a.consts;
     Coef<T> k;
     k.tau = (T)c.tau; k.eps1 = (T)c.eps1; k.eps2 = (T)c.eps2; k.c1 = (T)c.c1; k.c2 = (T)c.c2;
     k.u = (T)c.u; k.o = (T)c.o;
-    // log2 of the rounded coefficients, for the closed-form column-0 values
-    double lgs[6] = {log2((double)k.eps1), log2((double)k.eps2), log2((double)k.u),
-                     log2((double)k.c1), log2((double)k.c2), log2((double)k.o)};
     for (;;) {
         int q = 0;
         if (lane == 0) q = atomicAdd(a.queue_head, 1);
-        q = __shfl(q, 0, kWave);
+        // wave-uniform from here on: scalar registers and scalar branches
+        q = __builtin_amdgcn_readfirstlane(q);
         if ((int64_t)q >= a.n_pairs) break;
-        const int64_t p = a.queue[q];
-        const int m = a.lens[a.pair_i[p]];
+        const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
+        const int m = __builtin_amdgcn_readfirstlane(a.lens[a.pair_i[p]]);
         int R = (m + kWave - 1) / kWave;
         if (R > RMAX) R = RMAX;
-        dispatch<1, RMAX, T>(R, a, lane, slot, tab, k, lgs, p);
+        dispatch<1, RMAX, T>(R, a, lane, slot, tab, k, p);
     }
 }
 
 // ------------------------------------------------------ tables (a2 step)
 // Builds the (e_hmm, w_pf) table and the scaled constants from the raw
 // parameters in FP64, rounding once to the kernel precision.
+// D(i,0) = sum_k c_k eps_k^(i-1) and o u^(i-1), as mantissa/exponent pairs:
+// log2 in FP64, exact power-of-two exponent split, mantissa rounded once
+__device__ void col0_entry(const DevParams* p, int i0, Col0* out) {
+    const int G = p->n_gap_classes;
+    const double d1 = p->gap_open[0], e1 = p->gap_extend[0];
+    const double d2 = G > 1 ? p->gap_open[1] : 0.0, e2 = G > 1 ? p->gap_extend[1] : 0.0;
+    const double c1 = d1 * (1.0 - e1), c2 = d2 * (1.0 - e2);
+    auto term = [&](double c, double e) -> double {  // log2(c e^i0), -inf if zero
+        if (c <= 0.0) return -(double)INFINITY;
+        if (i0 == 0) return log2(c);
+        if (e <= 0.0) return -(double)INFINITY;
+        return log2(c) + (double)i0 * log2(e);
+    };
+    const double a1 = term(c1, e1), a2 = term(c2, e2);
+    const double am = fmax(a1, a2);
+    Col0 r;
+    if (am == -INFINITY) {
+        r.mH = 0.0;
+        r.eH = 0;
+    } else {
+        const int E = (int)floor(am);
+        const double v = (a1 == -INFINITY ? 0.0 : exp2(a1 - E)) + (a2 == -INFINITY ? 0.0 : exp2(a2 - E));
+        r.mH = v;
+        r.eH = E;
+    }
+    const double o = exp(p->pf_gap_open / p->temperature), u = exp(p->pf_gap_extend / p->temperature);
+    const double ap = log2(o) + (i0 == 0 ? 0.0 : (double)i0 * log2(u));
+    const int EPp = (int)floor(ap);
+    r.mP = exp2(ap - EPp);
+    r.eP = EPp;
+    *out = r;
+}
+
 template <typename T>
 __global__ void k_tables(const DevParams* __restrict__ p, typename Pair2<T>::type* __restrict__ tab,
-                         DevConsts* __restrict__ c) {
+                         DevConsts* __restrict__ c, Col0* __restrict__ col0, int rows) {
+    for (int i = (blockIdx.x - 1) * blockDim.x + threadIdx.x; blockIdx.x > 0 && i < rows;
+         i += (gridDim.x - 1) * blockDim.x)
+        col0_entry(p, i, &col0[i]);
+    if (blockIdx.x > 0) return;
     using V2 = typename Pair2<T>::type;
     const int t = threadIdx.x;
     __shared__ double qx[20], qy[20];
@@ -784,11 +867,15 @@ __global__ void k_gather(int64_t P, const int64_t* __restrict__ nnz_off, const i
 }
 
 // ================================================================ host side
-hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, int fp64, hipStream_t s) {
+hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, void* col0, int rows, int fp64, hipStream_t s) {
+    int blocks = 1 + (rows + 255) / 256;
+    if (blocks > 65) blocks = 65;
     if (fp64)
-        hipLaunchKernelGGL(k_tables<double>, dim3(1), dim3(256), 0, s, p, reinterpret_cast<double2*>(tab), c);
+        hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, s, p, reinterpret_cast<double2*>(tab), c,
+                           reinterpret_cast<Col0*>(col0), rows);
     else
-        hipLaunchKernelGGL(k_tables<float>, dim3(1), dim3(256), 0, s, p, reinterpret_cast<float2*>(tab), c);
+        hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, s, p, reinterpret_cast<float2*>(tab), c,
+                           reinterpret_cast<Col0*>(col0), rows);
     return hipGetLastError();
 }
 
@@ -890,6 +977,7 @@ int pairs_blocks_per_cu(int rmax, int fp64) {
     }
 }
 
+size_t col0_bytes() { return sizeof(Col0); }
 size_t fwd_bnd_bytes(int fp64) { return fp64 ? sizeof(FwdBnd<double>) : sizeof(FwdBnd<float>); }
 size_t bwd_bnd_bytes(int fp64) { return fp64 ? sizeof(BwdBnd<double>) : sizeof(BwdBnd<float>); }
 

@@ -48,6 +48,7 @@ struct PairArgs {
     int64_t n_pairs;
     int* queue_head;
     const void* tab;            // [kTabRows * kTabW] (e_hmm, w_pf) pairs
+    const void* col0;           // per row: D(i,0) of both models
     const DevConsts* consts;
     float thresh;
     int cap;                    // staging entries per row
@@ -73,7 +74,9 @@ struct PairArgs {
 };
 
 // kernels launched by the host code (qp_device.hip)
-hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, int fp64, hipStream_t s);
+hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, void* col0, int rows, int fp64,
+                         hipStream_t s);
+size_t col0_bytes();
 hipError_t launch_reset(int* ints, int n_ints, hipStream_t s);
 hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j,
                         int64_t n_pairs, int32_t* pair_i, int32_t* pair_j, int64_t* rows1, int32_t* key,

@@ -80,8 +80,8 @@ def test_c1_all_pairs(B, params):
     _c1_all_pairs(B, params, 0)
 
 
-@pytest.mark.skip(reason="a threshold-1e-30 run went silent for 180 s on the GPU and was killed; the cause is "
-                         "not yet identified, so this case stays off the GPU")
+@pytest.mark.skip(reason="a run at threshold 1e-30 exceeded its time limit and the cause is not yet "
+                         "identified; the case stays disabled until it is")
 @pytest.mark.parametrize("prec", [0, 1])
 def test_c1_dense_posteriors(B, params, prec):
     """Threshold 1e-30: the CSR holds every posterior the oracle has above
