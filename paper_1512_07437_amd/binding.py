@@ -295,3 +295,52 @@ def device_inputs(seqs: Sequence[np.ndarray], device: str = "cuda:0"):
         off[1:] = np.cumsum(lens)[:-1]
     cat = np.concatenate([np.asarray(s, dtype=np.uint8) for s in seqs]) if len(seqs) else np.zeros(1, np.uint8)
     return torch.from_numpy(cat).to(device), torch.from_numpy(off).to(device)
+
+
+class Server:
+    """Serving loop (qp_server_*): submit families, wait for tickets."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, n_streams: int = 4):
+        cfg = qp_server_config(int(hbm_budget_bytes), int(max_slots), int(n_streams))
+        self.handle = ctypes.c_void_p()
+        _check(lib.qp_server_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
+
+    def submit(self, seqs: Sequence[np.ndarray], params: qp_params, thresh: float) -> int:
+        keep, arr, lens = _seq_array(seqs)
+        t = ctypes.c_uint64()
+        _check(lib.qp_server_submit(self.handle, arr, lens.ctypes.data_as(_P(ctypes.c_int32)), len(keep),
+                                    ctypes.byref(params), ctypes.c_float(thresh), ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """Returns (result dict, times dict); raises QpError (QP_EBUSY /
+        QP_ETIMEDOUT if not ready)."""
+        out = _P(qp_result)()
+        tm = qp_request_times()
+        st = lib.qp_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_ms), ctypes.byref(out),
+                                ctypes.byref(tm))
+        _check(st)
+        try:
+            res = result_to_dict(out.contents)
+        finally:
+            lib.qp_result_free(out)
+        return res, dict(submit_s=tm.submit_s, admit_s=tm.admit_s, done_s=tm.done_s, cells=int(tm.cells))
+
+    def cancel(self, ticket: int) -> int:
+        return int(lib.qp_server_cancel(self.handle, ctypes.c_uint64(ticket)))
+
+    def stats(self):
+        q, f, d, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.qp_server_stats(self.handle, ctypes.byref(q), ctypes.byref(f), ctypes.byref(d), ctypes.byref(b)))
+        return dict(queued=q.value, in_flight=f.value, finished=d.value, bytes_in_use=b.value)
+
+    def close(self):
+        if self.handle:
+            lib.qp_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -38,6 +38,13 @@ qp_status fail(qp_status st, const char* fmt, ...) {
     } while (0)
 
 constexpr int kNumEventSets = 8;
+// layout of the plan's int counters
+constexpr int kIntHeads = 0;                          // [kClasses] queue heads
+constexpr int kIntFlags = 12;                         // overflow flags
+constexpr int kIntHist = 16;                          // [kKeyBins]
+constexpr int kIntFill = kIntHist + qp::kKeyBins;     // [kKeyBins]
+constexpr int kIntPool = kIntFill + qp::kKeyBins;     // 64-bit pool head
+constexpr int kNumInts = kIntPool + 2;
 
 // QP_TRACE=1 prints each host step of a call to stderr
 bool trace_on() {
@@ -84,6 +91,11 @@ int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
 }  // namespace
 
+qp_status qp::set_error(qp_status st, const char* msg) {
+    g_err = msg;
+    return st;
+}
+
 // ----------------------------------------------------------------- plan
 struct qp_plan {
     int device = 0;
@@ -95,11 +107,20 @@ struct qp_plan {
     qp_params params{};
     float thresh = 0.f;
     int fp64 = 0;
-    int rmax = 1, nb_max = 1, mmax = 1, nmax = 1, cap = 1;
-    int grid = 1;
+    int mmax = 1, nmax = 1;
     int64_t total_rows = 0;
     int64_t pool_cap = 0;
-    qp::PairArgs args{};
+    qp::PairArgs args{};  // fields shared by every class launch
+    // one persistent launch per kernel class present in the family
+    struct ClassPlan {
+        int64_t pairs = 0, cells = 0;
+        int mmax = 1, nmax = 1, R = 1, nb_max = 1, cap = 1, grid = 0;
+        qp::PairArgs args{};
+        char* d_scratch = nullptr;
+    } cls[qp::kClasses];
+    int n_side = 0;
+    hipStream_t side[3] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[3] = {};
     // device memory (one allocation each; freed in destroy)
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
@@ -114,7 +135,7 @@ struct qp_plan {
     int32_t* d_pj = nullptr;
     int64_t* d_rowoff = nullptr;
     int32_t* d_key = nullptr;
-    int* d_ints = nullptr;   // queue head, flags, hist, bin fill, pool head (as 2 ints)
+    int* d_ints = nullptr;   // queue heads, flags, hist, bin fill, pool head (as 2 ints)
     int n_ints = 0;
     int* d_bin_start = nullptr;
     int32_t* d_queue = nullptr;
@@ -128,7 +149,6 @@ struct qp_plan {
     double* d_dist = nullptr;
     double* d_logz = nullptr;
     int64_t* d_scan_tmp = nullptr;
-    char* d_scratch = nullptr;
     // graph and timing
     bool use_graph = true;
     bool graph_broken = false;
@@ -143,15 +163,21 @@ struct qp_plan {
     int64_t n_timed = 0;
     hipStream_t last_stream = nullptr;
     bool ran = false;
+    int last_g = -1;     // event set of the last run
     int64_t last_nnz = 0;
 };
 
 namespace {
 
 template <typename T>
-qp_status dalloc(qp_plan* pl, T** out, int64_t count) {
-    void* p = nullptr;
+qp_status dalloc(qp_plan* pl, T** out, int64_t count, int64_t* dry) {
     const int64_t bytes = std::max<int64_t>(count, 1) * (int64_t)sizeof(T);
+    if (dry) {  // size accounting only
+        *dry += (bytes + 255) & ~int64_t(255);
+        *out = nullptr;
+        return QP_OK;
+    }
+    void* p = nullptr;
     hipError_t e = hipMalloc(&p, (size_t)bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -181,35 +207,59 @@ qp_status validate_lens(const int32_t* lens, int32_t n) {
     return QP_OK;
 }
 
-// sizes of one per-wave scratch slot
-void size_slot(qp_plan* pl) {
+// sizes of one per-wave scratch slot of a kernel class
+void size_slot(const qp_plan* pl, qp_plan::ClassPlan* c) {
+    qp::PairArgs& a = c->args;
     const int64_t v2 = pl->fp64 ? 16 : 8;
-    const int64_t steps = (int64_t)pl->nmax + qp::kWave - 1;
-    pl->args.spill_band_stride = steps * qp::kWave * pl->rmax;
-    pl->args.exps_band_stride = steps * qp::kWave;
-    pl->args.bnd_stride = pl->nmax + 2;
-    int64_t off = align256(pl->nb_max * pl->args.spill_band_stride * v2);
-    pl->args.off_exps = off;
-    off += align256(pl->nb_max * pl->args.exps_band_stride * 8);
-    pl->args.off_fb = off;
-    off += align256(2 * pl->args.bnd_stride * (int64_t)qp::fwd_bnd_bytes(pl->fp64));
-    pl->args.off_bb = off;
-    off += align256(2 * pl->args.bnd_stride * (int64_t)qp::bwd_bnd_bytes(pl->fp64));
-    pl->args.off_stage_col = off;
-    off += align256((int64_t)pl->mmax * pl->cap * 4);
-    pl->args.off_stage_val = off;
-    off += align256((int64_t)pl->mmax * pl->cap * 4);
-    pl->args.slot_bytes = off;
+    const int64_t steps = (int64_t)c->nmax + qp::kWave - 1;
+    a.spill_band_stride = steps * qp::kWave * c->R;
+    a.exps_band_stride = steps * qp::kWave;
+    a.bnd_stride = c->nmax + 2;
+    int64_t off = align256(c->nb_max * a.spill_band_stride * v2);
+    a.off_exps = off;
+    off += align256(c->nb_max * a.exps_band_stride * 8);
+    a.off_fb = off;
+    off += align256(2 * a.bnd_stride * (int64_t)qp::fwd_bnd_bytes(pl->fp64));
+    a.off_bb = off;
+    off += align256(2 * a.bnd_stride * (int64_t)qp::bwd_bnd_bytes(pl->fp64));
+    a.off_stage_col = off;
+    off += align256((int64_t)c->mmax * c->cap * 4);
+    a.off_stage_val = off;
+    off += align256((int64_t)c->mmax * c->cap * 4);
+    a.slot_bytes = off;
 }
 
 }  // namespace
 
-// allocation of all plan buffers (needs pool_cap and grid)
-static qp_status plan_alloc_all(qp_plan* pl) {
+// per-class launch arguments: the shared fields plus the class's scratch
+static void set_class_args(qp_plan* pl) {
+    for (int c = 0; c < qp::kClasses; ++c) {
+        qp_plan::ClassPlan& cp = pl->cls[c];
+        if (cp.grid == 0) continue;
+        qp::PairArgs a = pl->args;
+        a.cls = c;
+        a.cap = cp.cap;
+        a.scratch = cp.d_scratch;
+        a.slot_bytes = cp.args.slot_bytes;
+        a.off_exps = cp.args.off_exps;
+        a.off_fb = cp.args.off_fb;
+        a.off_bb = cp.args.off_bb;
+        a.off_stage_col = cp.args.off_stage_col;
+        a.off_stage_val = cp.args.off_stage_val;
+        a.spill_band_stride = cp.args.spill_band_stride;
+        a.exps_band_stride = cp.args.exps_band_stride;
+        a.bnd_stride = cp.args.bnd_stride;
+        cp.args = a;
+    }
+}
+
+// allocation of all plan buffers (needs pool_cap and grids); with `dry`
+// only adds up the bytes it would allocate
+static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     const int64_t P = pl->P;
     qp_status st;
 #define ALLOC(ptr, cnt) \
-    if ((st = dalloc(pl, &(ptr), (cnt))) != QP_OK) return st
+    if ((st = dalloc(pl, &(ptr), (cnt), dry)) != QP_OK) return st
     ALLOC(pl->d_params, 1);
     {
         char* t = nullptr;
@@ -231,7 +281,7 @@ static qp_status plan_alloc_all(qp_plan* pl) {
     ALLOC(pl->d_pj, P);
     ALLOC(pl->d_rowoff, P + 1);
     ALLOC(pl->d_key, P);
-    pl->n_ints = 2 + 2 * qp::kKeyBins + 2;
+    pl->n_ints = kNumInts;
     ALLOC(pl->d_ints, pl->n_ints);
     ALLOC(pl->d_bin_start, qp::kKeyBins);
     ALLOC(pl->d_queue, P);
@@ -245,8 +295,11 @@ static qp_status plan_alloc_all(qp_plan* pl) {
     ALLOC(pl->d_dist, P);
     ALLOC(pl->d_logz, 2 * P);
     ALLOC(pl->d_scan_tmp, qp::scan_tmp_elems(P + 1) + 8);
-    ALLOC(pl->d_scratch, (int64_t)pl->grid * qp::kWavesPerBlock * pl->args.slot_bytes);
+    for (int c = 0; c < qp::kClasses; ++c)
+        if (pl->cls[c].grid > 0)
+            ALLOC(pl->cls[c].d_scratch, (int64_t)pl->cls[c].grid * qp::kWavesPerBlock * pl->cls[c].args.slot_bytes);
 #undef ALLOC
+    if (dry) return QP_OK;
     HIP_TRY(hipMemcpy(pl->d_lens, pl->lens.data(), sizeof(int32_t) * pl->n, hipMemcpyHostToDevice));
     if (!pl->all_pairs) {
         HIP_TRY(hipMemcpy(pl->d_list_i, pl->list_i.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
@@ -272,12 +325,13 @@ static qp_status plan_alloc_all(qp_plan* pl) {
     a.pair_j = pl->d_pj;
     a.queue = pl->d_queue;
     a.n_pairs = P;
-    a.queue_head = pl->d_ints;
+    a.queue_head = pl->d_ints + kIntHeads;
+    a.hist = pl->d_ints + kIntHist;
+    a.bin_start = pl->d_bin_start;
     a.tab = pl->d_tab;
     a.col0 = pl->d_col0;
     a.consts = pl->d_consts;
     a.thresh = pl->thresh;
-    a.cap = pl->cap;
     a.row_off = pl->d_rowoff;
     a.row_ptr = pl->d_rowptr;
     a.pair_nnz = pl->d_nnz;
@@ -285,11 +339,11 @@ static qp_status plan_alloc_all(qp_plan* pl) {
     a.pool_col = pl->d_pool_col;
     a.pool_val = pl->d_pool_val;
     a.pool_cap = pl->pool_cap;
-    a.pool_head = reinterpret_cast<unsigned long long*>(pl->d_ints + 2 + 2 * qp::kKeyBins);
+    a.pool_head = reinterpret_cast<unsigned long long*>(pl->d_ints + kIntPool);
     a.dist = pl->d_dist;
     a.logz = pl->d_logz;
-    a.flags = pl->d_ints + 1;
-    a.scratch = pl->d_scratch;
+    a.flags = pl->d_ints + kIntFlags;
+    set_class_args(pl);
     return QP_OK;
 }
 
@@ -306,12 +360,31 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, hipEvent_t* ev, bo
     HIP_TRY(qp::launch_reset(pl->d_ints, pl->n_ints, s));
     HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->d_col0, pl->mmax, pl->fp64, s));
     HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
-                             pl->d_key, pl->d_ints + 2, pl->d_nnz, s));
-    HIP_TRY(qp::launch_bins(pl->d_ints + 2, pl->d_bin_start, s));
-    HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + 2 + qp::kKeyBins, pl->d_queue, s));
+                             pl->d_key, pl->d_ints + kIntHist, pl->d_nnz, s));
+    HIP_TRY(qp::launch_bins(pl->d_ints + kIntHist, pl->d_bin_start, s));
+    HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + kIntFill, pl->d_queue, s));
     HIP_TRY(qp::scan_i64(pl->d_rowoff, P + 1, pl->d_scan_tmp, s));
     if (ev) HIP_TRY(record(ev[1], s, capturing));
-    HIP_TRY(qp::launch_pairs(pl->rmax, pl->fp64, pl->grid, pl->args, s));
+    // the kernel classes run concurrently on the side streams (fork / join)
+    int present[qp::kClasses], np = 0;
+    for (int c = qp::kClasses - 1; c >= 0; --c)
+        if (pl->cls[c].grid > 0) present[np++] = c;
+    if (np == 1 || pl->n_side == 0) {
+        for (int q = 0; q < np; ++q)
+            HIP_TRY(qp::launch_pairs(present[q], pl->fp64, pl->cls[present[q]].grid, pl->cls[present[q]].args, s));
+    } else {
+        HIP_TRY(hipEventRecord(pl->fork_ev, s));
+        const int ns = std::min(np, pl->n_side);
+        for (int q = 0; q < ns; ++q) HIP_TRY(hipStreamWaitEvent(pl->side[q], pl->fork_ev, 0));
+        for (int q = 0; q < np; ++q) {
+            const int c = present[q];
+            HIP_TRY(qp::launch_pairs(c, pl->fp64, pl->cls[c].grid, pl->cls[c].args, pl->side[q % ns]));
+        }
+        for (int q = 0; q < ns; ++q) {
+            HIP_TRY(hipEventRecord(pl->join_ev[q], pl->side[q]));
+            HIP_TRY(hipStreamWaitEvent(s, pl->join_ev[q], 0));
+        }
+    }
     if (ev) HIP_TRY(record(ev[2], s, capturing));
     HIP_TRY(qp::scan_i64(pl->d_nnz, P + 1, pl->d_scan_tmp, s));
     HIP_TRY(qp::launch_gather(P, pl->d_nnz, pl->d_base, pl->d_pool_col, pl->d_pool_val, pl->d_col,
@@ -423,9 +496,13 @@ qp_status qp_params_check(const qp_params* p) {
     return QP_OK;
 }
 
-qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+}  // extern "C"
+
+// Shape of a plan: validation, per-class work, grids and sizes; no device
+// memory yet.  wave_budget > 0 caps the resident waves of all its classes.
+qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
                          int64_t n_pairs, const qp_params* params, float thresh, int64_t nnz_capacity,
-                         qp_plan** plan) {
+                         int64_t wave_budget, qp_plan** plan) {
     if (!plan) return fail(QP_EINVAL, "plan is NULL");
     *plan = nullptr;
     qp_status st = validate_lens(lens, n);
@@ -463,55 +540,84 @@ qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     pl->thresh = thresh;
     pl->fp64 = params->precision == QP_FP64 ? 1 : 0;
 
-    // shape of the work: longest rows / columns over the pairs
-    int mmax = 1, nmax = 1;
+    // shape of the work per kernel class: pairs, cells, longest rows / columns
     int64_t rows = 0, est = 0;
     const double inv = std::floor(1.0 / (double)thresh);
     const int per_row = (int)std::max(1.0, std::min(8.0, inv));
+    auto count = [&](int32_t m, int32_t c) {
+        qp_plan::ClassPlan& cp = pl->cls[qp::pair_class(m)];
+        cp.pairs += 1;
+        cp.cells += (int64_t)m * c;
+        cp.mmax = std::max(cp.mmax, m);
+        cp.nmax = std::max(cp.nmax, c);
+        pl->mmax = std::max(pl->mmax, m);
+        pl->nmax = std::max(pl->nmax, c);
+        rows += m + 1;
+        est += (int64_t)m * std::min(per_row, c);
+    };
     if (all) {
-        for (int32_t i = 0; i + 1 < n; ++i) {
-            mmax = std::max(mmax, lens[i]);
-            rows += (int64_t)(n - 1 - i) * (lens[i] + 1);
-        }
-        for (int32_t j = 1; j < n; ++j) nmax = std::max(nmax, lens[j]);
         for (int32_t i = 0; i + 1 < n; ++i)
-            for (int32_t j = i + 1; j < n; ++j) est += (int64_t)lens[i] * std::min(per_row, lens[j]);
+            for (int32_t j = i + 1; j < n; ++j) count(lens[i], lens[j]);
     } else {
-        for (int64_t k = 0; k < P; ++k) {
-            const int32_t m = lens[pair_i[k]], c = lens[pair_j[k]];
-            mmax = std::max(mmax, m);
-            nmax = std::max(nmax, c);
-            rows += m + 1;
-            est += (int64_t)m * std::min(per_row, c);
-        }
+        for (int64_t k = 0; k < P; ++k) count(lens[pair_i[k]], lens[pair_j[k]]);
     }
-    pl->mmax = mmax;
-    pl->nmax = nmax;
     pl->total_rows = rows;
-    pl->rmax = std::min(qp::kRMax, std::max(1, (mmax + qp::kWave - 1) / qp::kWave));
-    pl->nb_max = (mmax + qp::kWave * pl->rmax - 1) / (qp::kWave * pl->rmax);
-    pl->cap = (int)std::max(1.0, std::min((double)nmax, inv + 1.0));
     pl->pool_cap = nnz_capacity > 0 ? nnz_capacity : std::max<int64_t>(est + 1024, 1024);
-    size_slot(pl);
 
-    // persistent grid: enough waves to fill every SIMD at the kernel's
-    // occupancy, bounded by the pair count and by a scratch budget
+    // persistent grid per class: enough waves to fill every SIMD at the
+    // kernel's occupancy, bounded by the class's pair count; all classes
+    // together stay within half of the free device memory
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         (void)hipGetLastError();
         free_b = (size_t)64 << 30;
     }
-    const int per_cu = qp::pairs_blocks_per_cu(pl->rmax, pl->fp64);
-    int64_t grid = (int64_t)per_cu * n_cu;
-    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (P + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock));
+    int64_t want_bytes = 0;
+    for (int c = 0; c < qp::kClasses; ++c) {
+        qp_plan::ClassPlan& cp = pl->cls[c];
+        if (cp.pairs == 0) continue;
+        cp.R = qp::class_rows_per_lane(c);
+        const int H = qp::kWave * cp.R;
+        cp.nb_max = c == qp::kRMax ? (cp.mmax + H - 1) / H : 1;
+        cp.cap = (int)std::max(1.0, std::min((double)cp.nmax, inv + 1.0));
+        size_slot(pl, &cp);
+        const int per_cu = qp::pairs_blocks_per_cu(c, pl->fp64);
+        int64_t grid = (int64_t)per_cu * n_cu;
+        grid = std::min<int64_t>(grid, std::max<int64_t>(1, (cp.pairs + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock));
+        cp.grid = (int)grid;
+        want_bytes += grid * qp::kWavesPerBlock * cp.args.slot_bytes;
+    }
     const int64_t budget = (int64_t)(free_b / 2);
-    const int64_t per_block = pl->args.slot_bytes * qp::kWavesPerBlock;
-    if (grid * per_block > budget) grid = std::max<int64_t>(1, budget / per_block);
-    pl->grid = (int)grid;
+    if (want_bytes > budget) {
+        const double f = (double)budget / (double)want_bytes;
+        for (int c = 0; c < qp::kClasses; ++c)
+            if (pl->cls[c].grid > 0) pl->cls[c].grid = std::max(1, (int)(pl->cls[c].grid * f));
+    }
+    if (wave_budget > 0) {
+        int64_t waves = 0;
+        for (int c = 0; c < qp::kClasses; ++c) waves += (int64_t)pl->cls[c].grid * qp::kWavesPerBlock;
+        if (waves > wave_budget) {
+            const double f = (double)wave_budget / (double)waves;
+            for (int c = 0; c < qp::kClasses; ++c)
+                if (pl->cls[c].grid > 0) pl->cls[c].grid = std::max(1, (int)(pl->cls[c].grid * f));
+        }
+    }
+    *plan = pl;
+    return QP_OK;
+}
 
+// device bytes a shaped plan will hold
+int64_t qp::plan_bytes(qp_plan* pl) {
+    int64_t b = 0;
+    plan_alloc_all(pl, &b);
+    return b;
+}
+
+// allocate a shaped plan's device memory, streams and events
+qp_status qp::plan_materialize(qp_plan* pl) {
+    qp_status st;
     if ((st = plan_alloc_all(pl)) != QP_OK) {
         plan_free_device(pl);
-        delete pl;
         return st;
     }
     hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
@@ -519,14 +625,43 @@ qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         for (int g = 0; g < kNumEventSets && e == hipSuccess; ++g)
             for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipEventCreate(&pl->ev[g][q]);
     }
-    if (e != hipSuccess) {
-        plan_free_device(pl);
-        delete pl;
-        return fail(QP_EDEVICE, "stream/event creation failed: %s", hipGetErrorString(e));
+    int n_present = 0;
+    for (int c = 0; c < qp::kClasses; ++c) n_present += pl->cls[c].grid > 0;
+    if (e == hipSuccess && n_present > 1) {
+        pl->n_side = std::min(n_present, 3);
+        e = hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming);
+        for (int q = 0; q < pl->n_side && e == hipSuccess; ++q) {
+            e = hipStreamCreateWithFlags(&pl->side[q], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join_ev[q], hipEventDisableTiming);
+        }
     }
-    trace("plan: n=%d pairs=%lld rmax=%d bands<=%d mmax=%d nmax=%d cap=%d grid=%d slot=%lld B pool=%lld fp64=%d",
-          n, (long long)P, pl->rmax, pl->nb_max, mmax, nmax, pl->cap, pl->grid, (long long)pl->args.slot_bytes,
-          (long long)pl->pool_cap, pl->fp64);
+    if (e != hipSuccess) return fail(QP_EDEVICE, "stream/event creation failed: %s", hipGetErrorString(e));
+    if (trace_on()) {
+        trace("plan: n=%d pairs=%lld mmax=%d nmax=%d pool=%lld fp64=%d", pl->n, (long long)pl->P, pl->mmax, pl->nmax,
+              (long long)pl->pool_cap, pl->fp64);
+        for (int c = 0; c < qp::kClasses; ++c)
+            if (pl->cls[c].grid > 0)
+                trace("  class %d: R=%d bands<=%d pairs=%lld cells=%lld grid=%d slot=%lld B cap=%d", c,
+                      pl->cls[c].R, pl->cls[c].nb_max, (long long)pl->cls[c].pairs, (long long)pl->cls[c].cells,
+                      pl->cls[c].grid, (long long)pl->cls[c].args.slot_bytes, pl->cls[c].cap);
+    }
+    return QP_OK;
+}
+
+extern "C" {
+
+qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                         int64_t n_pairs, const qp_params* params, float thresh, int64_t nnz_capacity,
+                         qp_plan** plan) {
+    qp_plan* pl = nullptr;
+    qp_status st = qp::plan_shape(lens, n, pair_i, pair_j, n_pairs, params, thresh, nnz_capacity, 0, &pl);
+    if (st != QP_OK) return st;
+    if ((st = qp::plan_materialize(pl)) != QP_OK) {
+        std::string keep = g_err;
+        qp_plan_destroy(pl);
+        g_err = keep;
+        return st;
+    }
     *plan = pl;
     return QP_OK;
 }
@@ -564,6 +699,7 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
             trace("run: graph %d", g);
             HIP_TRY(hipGraphLaunch(pl->exec[g], s));
             pl->ev_pending[g] = true;
+            pl->last_g = g;
             pl->run_idx++;
             return QP_OK;
         }
@@ -572,6 +708,7 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
     qp_status st = enqueue_pipeline(pl, s, pl->ev[g]);
     if (st != QP_OK) return st;
     pl->ev_pending[g] = true;
+    pl->last_g = g;
     pl->run_idx++;
     return QP_OK;
 }
@@ -581,17 +718,22 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
     if (!pl->ran) return fail(QP_EINVAL, "plan has not been run");
     HIP_TRY(hipSetDevice(pl->device));
     trace("sync: waiting");
-    HIP_TRY(hipStreamSynchronize(pl->last_stream));
+    // the plan's own end event: other work queued behind it on the same
+    // stream (other families) is not waited for
+    if (pl->last_g >= 0 && pl->P > 0)
+        HIP_TRY(hipEventSynchronize(pl->ev[pl->last_g][3]));
+    else
+        HIP_TRY(hipStreamSynchronize(pl->last_stream));
     int64_t nnz = 0;
     int flags = 0;
     if (pl->P > 0) {
         HIP_TRY(hipMemcpy(&nnz, pl->d_nnz + pl->P, sizeof(int64_t), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(&flags, pl->d_ints + 1, sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&flags, pl->d_ints + kIntFlags, sizeof(int), hipMemcpyDeviceToHost));
     }
     pl->last_nnz = nnz;
     trace("sync: done nnz=%lld flags=%d", (long long)nnz, flags);
     if (flags & 2)
-        return fail(QP_EDEVICE, "a row held more than %d entries above the threshold (staging capacity)", pl->cap);
+        return fail(QP_EDEVICE, "a row held more entries above the threshold than its staging capacity");
     if ((flags & 1) || nnz > pl->pool_cap) {
         // grow the sparse output so that the next run fits
         const int64_t need = nnz + nnz / 16 + 1024;
@@ -621,6 +763,7 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
         pl->args.pool_col = pl->d_pool_col;
         pl->args.pool_val = pl->d_pool_val;
         pl->args.pool_cap = need;
+        set_class_args(pl);
         pl->cap_seqs = nullptr;  // recapture with the new buffers
         return fail(QP_ENOSPC, "sparse output needed %lld entries; capacity grown, run again", (long long)nnz);
     }
@@ -700,7 +843,7 @@ qp_status qp_plan_download(qp_plan* pl, qp_result** out) {
 qp_status qp_plan_timing(qp_plan* pl, double* kernel_ms, double* pipeline_ms, int64_t* n_runs, int32_t reset) {
     if (!pl) return fail(QP_EINVAL, "plan is NULL");
     HIP_TRY(hipSetDevice(pl->device));
-    if (pl->ran) HIP_TRY(hipStreamSynchronize(pl->last_stream));
+    if (pl->ran && pl->last_g >= 0) HIP_TRY(hipEventSynchronize(pl->ev[pl->last_g][3]));
     collect_timing(pl);
     if (kernel_ms) *kernel_ms = pl->n_timed ? pl->sum_kernel_ms / pl->n_timed : 0.0;
     if (pipeline_ms) *pipeline_ms = pl->n_timed ? pl->sum_pipe_ms / pl->n_timed : 0.0;
@@ -723,12 +866,17 @@ int64_t qp_plan_device_bytes(const qp_plan* pl) { return pl ? pl->device_bytes :
 void qp_plan_destroy(qp_plan* pl) {
     if (!pl) return;
     hipSetDevice(pl->device);
-    if (pl->ran && pl->last_stream) hipStreamSynchronize(pl->last_stream);
+    if (pl->ran && pl->last_g >= 0) hipEventSynchronize(pl->ev[pl->last_g][3]);
     plan_free_device(pl);
     for (int g = 0; g < kNumEventSets; ++g)
         for (int q = 0; q < 4; ++q)
             if (pl->ev[g][q]) hipEventDestroy(pl->ev[g][q]);
     if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
+    for (int q = 0; q < 3; ++q) {
+        if (pl->side[q]) hipStreamDestroy(pl->side[q]);
+        if (pl->join_ev[q]) hipEventDestroy(pl->join_ev[q]);
+    }
+    if (pl->fork_ev) hipEventDestroy(pl->fork_ev);
     delete pl;
 }
 

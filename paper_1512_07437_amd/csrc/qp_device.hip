@@ -486,9 +486,11 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             FP -= sp;
         }
     };
-    for (int t = 0; t < S; t += 2) {
+    for (int t = 0; t < S; ++t) {
         step(t, fa, ea, fb, eb);
-        if (t + 1 < S) step(t + 1, fb, eb, fa, ea);
+#pragma unroll
+        for (int r = 0; r < R; ++r) fa[r] = fb[r];
+        ea = eb;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -506,7 +508,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
 }
 
 // ------------------------------------------------------------ one pair
-template <int R, typename T>
+template <int R, typename T, bool MULTI>
 __device__ void process_pair(const PairArgs& a, int lane, char* slot, const typename Pair2<T>::type* tab,
                              const Coef<T>& k, int64_t p) {
     using V2 = typename Pair2<T>::type;
@@ -517,7 +519,7 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
     const uint8_t* x = a.seqs + a.seq_off[pi];
     const uint8_t* y = a.seqs + a.seq_off[pj];
     const int H = kWave * R;
-    const int nb = (m + H - 1) / H;
+    const int nb = MULTI ? (m + H - 1) / H : 1;
     V2* spill = reinterpret_cast<V2*>(slot);
     int2* exps = reinterpret_cast<int2*>(slot + a.off_exps);
     FwdBnd<T>* fb = reinterpret_cast<FwdBnd<T>*>(slot + a.off_fb);
@@ -536,7 +538,7 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
         int2* ex = exps + (int64_t)b * a.exps_band_stride;
         const FwdBnd<T>* fi = fb + (int64_t)((b + 1) & 1) * a.bnd_stride;
         FwdBnd<T>* fo = fb + (int64_t)(b & 1) * a.bnd_stride;
-        if (nb == 1)
+        if (!MULTI)
             fwd_band<R, T, true, true>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
         else if (b == 0)
             fwd_band<R, T, true, false>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
@@ -561,7 +563,7 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
 #define QP_BWD(F, Lb)                                                                                      \
     bwd_band<R, T, F, Lb>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH, ezP, a.thresh, \
                           a.cap, stage_col, stage_val, rp + 1, a.flags, a11)
-        if (nb == 1)
+        if (!MULTI)
             QP_BWD(true, true);
         else if (b == 0)
             QP_BWD(true, false);
@@ -613,20 +615,9 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
     __threadfence_block();
 }
 
-template <int RR, int RMAX, typename T>
-__device__ __forceinline__ void dispatch(int R, const PairArgs& a, int lane, char* slot,
-                                         const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p) {
-    if constexpr (RR > RMAX) {
-        return;
-    } else {
-        if (R == RR)
-            process_pair<RR, T>(a, lane, slot, tab, k, p);
-        else
-            dispatch<RR + 1, RMAX, T>(R, a, lane, slot, tab, k, p);
-    }
-}
-
-template <int RMAX, typename T>
+// One persistent launch per kernel class: waves pop pairs of their class
+// from the cost-ordered queue segment (most expensive first).
+template <int R, typename T, bool MULTI>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
     using V2 = typename Pair2<T>::type;
     __shared__ V2 tab[kTabRows * kTabW];
@@ -642,17 +633,19 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
     Coef<T> k;
     k.tau = (T)c.tau; k.eps1 = (T)c.eps1; k.eps2 = (T)c.eps2; k.c1 = (T)c.c1; k.c2 = (T)c.c2;
     k.u = (T)c.u; k.o = (T)c.o;
+    // this class's queue segment: keys [cls*kCostBins, cls*kCostBins + kCostBins)
+    const int k0 = a.cls * kCostBins, k1 = k0 + kCostBins - 1;
+    const int seg_begin = __builtin_amdgcn_readfirstlane(a.bin_start[k1]);
+    const int seg_end = __builtin_amdgcn_readfirstlane(a.bin_start[k0] + a.hist[k0]);
+    int* head = a.queue_head + a.cls;
     for (;;) {
         int q = 0;
-        if (lane == 0) q = atomicAdd(a.queue_head, 1);
+        if (lane == 0) q = atomicAdd(head, 1);
         // wave-uniform from here on: scalar registers and scalar branches
-        q = __builtin_amdgcn_readfirstlane(q);
-        if ((int64_t)q >= a.n_pairs) break;
+        q = __builtin_amdgcn_readfirstlane(q) + seg_begin;
+        if (q >= seg_end) break;
         const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
-        const int m = __builtin_amdgcn_readfirstlane(a.lens[a.pair_i[p]]);
-        int R = (m + kWave - 1) / kWave;
-        if (R > RMAX) R = RMAX;
-        dispatch<1, RMAX, T>(R, a, lane, slot, tab, k, p);
+        process_pair<R, T, MULTI>(a, lane, slot, tab, k, p);
     }
 }
 
@@ -774,8 +767,9 @@ __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32
     pj[p] = (int32_t)j;
     const int64_t m = lens[i], c = lens[j];
     rows1[p] = m + 1;
-    int kk = (int)(log2((double)(m * c)) * 16.0);
-    kk = kk < 0 ? 0 : (kk >= kKeyBins ? kKeyBins - 1 : kk);
+    int cb = (int)(log2((double)(m * c)) * 2.0);
+    cb = cb < 0 ? 0 : (cb >= kCostBins ? kCostBins - 1 : cb);
+    const int kk = pair_class((int)m) * kCostBins + cb;
     key[p] = kk;
     atomicAdd(&hist[kk], 1);
 }
@@ -929,51 +923,53 @@ hipError_t scan_i64(int64_t* d, int64_t n, int64_t* tmp, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int RMAX>
+template <int R, bool MULTI>
 static hipError_t launch_pairs_r(int fp64, int grid, const PairArgs& a, hipStream_t s) {
     if (fp64)
-        hipLaunchKernelGGL((k_pairs<RMAX, double>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
+        hipLaunchKernelGGL((k_pairs<R, double, MULTI>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_pairs<RMAX, float>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
+        hipLaunchKernelGGL((k_pairs<R, float, MULTI>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(int rmax, int fp64, int grid, const PairArgs& a, hipStream_t s) {
-    switch (rmax) {
-        case 1: return launch_pairs_r<1>(fp64, grid, a, s);
-        case 2: return launch_pairs_r<2>(fp64, grid, a, s);
-        case 3: return launch_pairs_r<3>(fp64, grid, a, s);
-        case 4: return launch_pairs_r<4>(fp64, grid, a, s);
-        case 5: return launch_pairs_r<5>(fp64, grid, a, s);
-        case 6: return launch_pairs_r<6>(fp64, grid, a, s);
-        case 7: return launch_pairs_r<7>(fp64, grid, a, s);
-        default: return launch_pairs_r<8>(fp64, grid, a, s);
+hipError_t launch_pairs(int cls, int fp64, int grid, const PairArgs& a, hipStream_t s) {
+    switch (cls) {
+        case 0: return launch_pairs_r<1, false>(fp64, grid, a, s);
+        case 1: return launch_pairs_r<2, false>(fp64, grid, a, s);
+        case 2: return launch_pairs_r<3, false>(fp64, grid, a, s);
+        case 3: return launch_pairs_r<4, false>(fp64, grid, a, s);
+        case 4: return launch_pairs_r<5, false>(fp64, grid, a, s);
+        case 5: return launch_pairs_r<6, false>(fp64, grid, a, s);
+        case 6: return launch_pairs_r<7, false>(fp64, grid, a, s);
+        case 7: return launch_pairs_r<8, false>(fp64, grid, a, s);
+        default: return launch_pairs_r<8, true>(fp64, grid, a, s);
     }
 }
 
-template <int RMAX>
+template <int R, bool MULTI>
 static int blocks_per_cu_r(int fp64) {
     int nb = 0;
     hipError_t e;
     if (fp64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs<RMAX, double>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs<R, double, MULTI>,
                                                          kWave * kWavesPerBlock, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs<RMAX, float>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs<R, float, MULTI>,
                                                          kWave * kWavesPerBlock, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-int pairs_blocks_per_cu(int rmax, int fp64) {
-    switch (rmax) {
-        case 1: return blocks_per_cu_r<1>(fp64);
-        case 2: return blocks_per_cu_r<2>(fp64);
-        case 3: return blocks_per_cu_r<3>(fp64);
-        case 4: return blocks_per_cu_r<4>(fp64);
-        case 5: return blocks_per_cu_r<5>(fp64);
-        case 6: return blocks_per_cu_r<6>(fp64);
-        case 7: return blocks_per_cu_r<7>(fp64);
-        default: return blocks_per_cu_r<8>(fp64);
+int pairs_blocks_per_cu(int cls, int fp64) {
+    switch (cls) {
+        case 0: return blocks_per_cu_r<1, false>(fp64);
+        case 1: return blocks_per_cu_r<2, false>(fp64);
+        case 2: return blocks_per_cu_r<3, false>(fp64);
+        case 3: return blocks_per_cu_r<4, false>(fp64);
+        case 4: return blocks_per_cu_r<5, false>(fp64);
+        case 5: return blocks_per_cu_r<6, false>(fp64);
+        case 6: return blocks_per_cu_r<7, false>(fp64);
+        case 7: return blocks_per_cu_r<8, false>(fp64);
+        default: return blocks_per_cu_r<8, true>(fp64);
     }
 }
 

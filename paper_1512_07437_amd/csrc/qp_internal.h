@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "qp.h"
+
 namespace qp {
 
 constexpr int kWave = 64;           // lanes per wavefront on CDNA
@@ -15,7 +17,17 @@ constexpr int kPadCode = 20;        // x code of rows past the end of a strip
 constexpr int kTabRows = 21;        // 20 residues + the padding row
 constexpr int kRMax = 8;            // largest rows-per-lane instantiation
 constexpr int kRescaleEvery = 8;    // steps between power-of-two rescales
-constexpr int kKeyBins = 1024;      // cost classes of the longest-first queue
+constexpr int kKeyBins = 1024;      // queue keys: kernel class x cost bin
+constexpr int kCostBins = 64;       // half-octave bins of m*n per kernel class
+constexpr int kClasses = 9;         // R = 1..8 single band, R = 8 banded
+
+// kernel class of a pair: rows per lane R = ceil(m/64) capped at 8; longer
+// rows are cut into bands of 64*8 and go to the banded class
+__host__ __device__ inline int pair_class(int m) {
+    const int R = (m + kWave - 1) / kWave;
+    return R <= kRMax ? R - 1 : kRMax;
+}
+__host__ __device__ inline int class_rows_per_lane(int c) { return c < kRMax ? c + 1 : kRMax; }
 
 // Model constants in the scaled-variable form used by the kernels, computed
 // on the device from the raw parameters (k_tables).
@@ -44,9 +56,12 @@ struct PairArgs {
     const int32_t* lens;
     const int32_t* pair_i;
     const int32_t* pair_j;
-    const int32_t* queue;       // pair ids in processing order
+    const int32_t* queue;       // pair ids in processing order (class-major)
     int64_t n_pairs;
-    int* queue_head;
+    int* queue_head;            // [kClasses] per-class queue heads
+    const int* hist;            // [kKeyBins] pairs per queue key
+    const int* bin_start;       // [kKeyBins] first queue slot of each key
+    int cls;                    // kernel class this launch serves
     const void* tab;            // [kTabRows * kTabW] (e_hmm, w_pf) pairs
     const void* col0;           // per row: D(i,0) of both models
     const DevConsts* consts;
@@ -87,11 +102,19 @@ hipError_t launch_fill_queue(int64_t n_pairs, const int32_t* key, const int* bin
 // exclusive scan of n int64 values in place; tmp must hold scan_tmp_elems(n)
 int64_t scan_tmp_elems(int64_t n);
 hipError_t scan_i64(int64_t* data, int64_t n, int64_t* tmp, hipStream_t s);
-hipError_t launch_pairs(int rmax, int fp64, int grid, const PairArgs& a, hipStream_t s);
-int pairs_blocks_per_cu(int rmax, int fp64);
+hipError_t launch_pairs(int cls, int fp64, int grid, const PairArgs& a, hipStream_t s);
+int pairs_blocks_per_cu(int cls, int fp64);
 hipError_t launch_gather(int64_t n_pairs, const int64_t* nnz_off, const int64_t* pair_base, const int32_t* pool_col, const float* pool_val,
                          int32_t* col, float* val, int64_t cap, hipStream_t s);
 size_t fwd_bnd_bytes(int fp64);
 size_t bwd_bnd_bytes(int fp64);
+
+// plan building blocks shared with the serving loop (qp_api.cpp)
+qp_status plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j, int64_t n_pairs,
+                     const qp_params* params, float thresh, int64_t nnz_capacity, int64_t wave_budget,
+                     qp_plan** plan);
+int64_t plan_bytes(qp_plan* pl);
+qp_status plan_materialize(qp_plan* pl);
+qp_status set_error(qp_status st, const char* msg);
 
 }  // namespace qp

@@ -1,21 +1,406 @@
-// Serving loop of the posterior engine (see include/qp.h): placeholder until
-// the scheduler lands; every call reports that serving is unavailable.
+// Serving loop of the posterior engine (see include/qp.h): families arrive
+// over time, are admitted when a slot is free and the device-memory budget
+// covers their workspace and outputs, run concurrently on a pool of streams
+// (continuous batching: a family admitted while others run overlaps with
+// them on the device), and are handed back as host results with their
+// submit / admit / done times.  The stage-I work of every family is the same
+// computation as qp_posteriors; only the scheduling differs, so a family's
+// result does not depend on what else is in flight.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
 #include "qp.h"
+#include "qp_internal.h"
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration_cast<duration<double>>(steady_clock::now().time_since_epoch()).count();
+}
+
+enum class St { Queued, Running, Done, Canceled };
+
+struct Request {
+    uint64_t ticket = 0;
+    std::vector<uint8_t> codes;   // all sequences concatenated
+    std::vector<int64_t> off;     // start of each sequence
+    std::vector<int32_t> lens;
+    qp_params params{};
+    float thresh = 0.f;
+    qp_plan* plan = nullptr;      // shaped at submit, materialised at admission
+    int64_t bytes = 0;            // device bytes while running
+    int64_t cells = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    uint8_t* d_codes = nullptr;
+    int64_t* d_off = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    qp_result* result = nullptr;
+    qp_status status = QP_OK;
+    std::string error;
+    St state = St::Queued;
+};
+
+}  // namespace
+
+struct qp_server {
+    qp_server_config cfg{};
+    int device = 0;
+    int64_t wave_budget = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::vector<Request*> running;
+    std::map<uint64_t, Request*> all;
+    int64_t bytes_in_use = 0, finished = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::vector<hipStream_t> streams;
+    int next_stream = 0;
+    std::thread thr;
+};
+
+namespace {
+
+void release_device(Request* r) {
+    if (r->plan) qp_plan_destroy(r->plan);
+    r->plan = nullptr;
+    if (r->d_codes) hipFree(r->d_codes);
+    if (r->d_off) hipFree(r->d_off);
+    if (r->done_ev) hipEventDestroy(r->done_ev);
+    r->d_codes = nullptr;
+    r->d_off = nullptr;
+    r->done_ev = nullptr;
+}
+
+// admission: allocate, upload, enqueue the whole pipeline on the stream
+qp_status launch(qp_server* s, Request* r) {
+    qp_status st = qp::plan_materialize(r->plan);
+    if (st != QP_OK) return st;
+    qp_plan_set_graph(r->plan, 0);
+    const int64_t tot = std::max<int64_t>(1, (int64_t)r->codes.size());
+    hipError_t e = hipMalloc((void**)&r->d_codes, (size_t)tot);
+    if (e == hipSuccess) e = hipMalloc((void**)&r->d_off, sizeof(int64_t) * std::max<size_t>(1, r->off.size()));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return qp::set_error(QP_ENOMEM, "device allocation for an admitted family failed");
+    }
+    if (!r->codes.empty())
+        e = hipMemcpyAsync(r->d_codes, r->codes.data(), r->codes.size(), hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess && !r->off.empty())
+        e = hipMemcpyAsync(r->d_off, r->off.data(), sizeof(int64_t) * r->off.size(), hipMemcpyHostToDevice,
+                           r->stream);
+    if (e != hipSuccess) return qp::set_error(QP_EDEVICE, "host-to-device copy failed");
+    st = qp_plan_run(r->plan, r->d_codes, r->d_off, r->stream);
+    if (st != QP_OK) return st;
+    if (hipEventRecord(r->done_ev, r->stream) != hipSuccess)
+        return qp::set_error(QP_EDEVICE, "event record failed");
+    return QP_OK;
+}
+
+// a family's device work has finished: download (or re-run once if the
+// sparse output outgrew its estimate)
+bool complete(qp_server* s, Request* r) {
+    qp_status st = qp_plan_download(r->plan, &r->result);
+    if (st == QP_ENOSPC) {
+        // the plan grew its output; run again on the same stream
+        st = qp_plan_run(r->plan, r->d_codes, r->d_off, r->stream);
+        if (st == QP_OK && hipEventRecord(r->done_ev, r->stream) == hipSuccess) {
+            std::lock_guard<std::mutex> g(s->mu);
+            const int64_t nb = qp_plan_device_bytes(r->plan) + (int64_t)r->codes.size() + 8 * (int64_t)r->off.size();
+            s->bytes_in_use += nb - r->bytes;
+            r->bytes = nb;
+            return false;  // still running
+        }
+    }
+    r->status = st;
+    if (st != QP_OK) r->error = qp_last_error();
+    return true;
+}
+
+void scheduler(qp_server* s) {
+    hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // admit in arrival order while a slot and the memory budget allow
+        while (!s->queue.empty() && (int)s->running.size() < s->cfg.max_slots &&
+               s->bytes_in_use + s->queue.front()->bytes <= s->cfg.hbm_budget_bytes) {
+            Request* r = s->queue.front();
+            s->queue.pop_front();
+            r->state = St::Running;
+            r->t_admit = now_s();
+            r->stream = s->streams[s->next_stream++ % s->streams.size()];
+            s->running.push_back(r);
+            s->bytes_in_use += r->bytes;
+            lk.unlock();
+            const qp_status st = launch(s, r);
+            std::string err = st == QP_OK ? "" : qp_last_error();
+            lk.lock();
+            if (st != QP_OK) {
+                if (r->stream) hipStreamSynchronize(r->stream);
+                release_device(r);
+                r->status = st;
+                r->error = err;
+                r->state = St::Done;
+                r->t_done = now_s();
+                s->bytes_in_use -= r->bytes;
+                s->running.erase(std::find(s->running.begin(), s->running.end(), r));
+                s->finished++;
+                s->cv_done.notify_all();
+            }
+        }
+        // retire finished families
+        bool any_done = false;
+        for (size_t q = 0; q < s->running.size();) {
+            Request* r = s->running[q];
+            if (hipEventQuery(r->done_ev) != hipSuccess) {
+                ++q;
+                continue;
+            }
+            lk.unlock();
+            const bool fin = complete(s, r);
+            lk.lock();
+            if (!fin) {
+                ++q;
+                continue;
+            }
+            release_device(r);
+            r->t_done = now_s();
+            r->state = St::Done;
+            s->bytes_in_use -= r->bytes;
+            s->running.erase(s->running.begin() + q);
+            s->finished++;
+            any_done = true;
+        }
+        if (any_done) s->cv_done.notify_all();
+        if (s->stop && s->running.empty() && s->queue.empty()) break;
+        if (s->running.empty())
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        else
+            s->cv_work.wait_for(lk, std::chrono::microseconds(100));
+    }
+}
+
+}  // namespace
 
 extern "C" {
-qp_status qp_server_create(const qp_server_config*, qp_server** s) {
-    if (s) *s = nullptr;
-    return QP_EDEVICE;
+
+qp_status qp_server_create(const qp_server_config* cfg, qp_server** out) {
+    if (!out) return qp::set_error(QP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return qp::set_error(QP_EINVAL, "config is NULL");
+    if (cfg->hbm_budget_bytes <= 0) return qp::set_error(QP_EINVAL, "hbm_budget_bytes must be > 0");
+    if (cfg->max_slots < 1 || cfg->max_slots > 64) return qp::set_error(QP_EINVAL, "max_slots must be in 1..64");
+    if (cfg->n_streams < 1 || cfg->n_streams > 16) return qp::set_error(QP_EINVAL, "n_streams must be in 1..16");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return qp::set_error(QP_EDEVICE, "no HIP device available");
+    }
+    qp_server* s = new (std::nothrow) qp_server();
+    if (!s) return qp::set_error(QP_ENOMEM, "out of host memory");
+    s->cfg = *cfg;
+    hipGetDevice(&s->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
+        delete s;
+        return qp::set_error(QP_EDEVICE, "device properties unavailable");
+    }
+    // each admitted family gets an equal share of the resident waves
+    // (three per SIMD), twice over so that a finishing family's share is
+    // taken up by the others
+    s->wave_budget = std::max<int64_t>(256, (int64_t)prop.multiProcessorCount * 4 * 3 * 2 / cfg->max_slots);
+    for (int q = 0; q < cfg->n_streams; ++q) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (hipStream_t x : s->streams) hipStreamDestroy(x);
+            delete s;
+            return qp::set_error(QP_EDEVICE, "stream creation failed");
+        }
+        s->streams.push_back(st);
+    }
+    s->thr = std::thread(scheduler, s);
+    *out = s;
+    return QP_OK;
 }
-qp_status qp_server_submit(qp_server*, const uint8_t* const*, const int32_t*, int32_t, const qp_params*, float,
-                           uint64_t*) {
-    return QP_EINVAL;
+
+qp_status qp_server_submit(qp_server* s, const uint8_t* const* seqs, const int32_t* lens, int32_t n,
+                           const qp_params* params, float thresh, uint64_t* ticket) {
+    if (!s || !ticket) return qp::set_error(QP_EINVAL, "server or ticket is NULL");
+    *ticket = 0;
+    if (n < 0 || (n > 0 && (!seqs || !lens))) return qp::set_error(QP_EINVAL, "bad family arguments");
+    Request* r = new (std::nothrow) Request();
+    if (!r) return qp::set_error(QP_ENOMEM, "out of host memory");
+    r->t_submit = now_s();
+    int64_t tot = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!seqs[i] || lens[i] < 1) {
+            delete r;
+            return qp::set_error(QP_EINVAL, "sequence is NULL or empty");
+        }
+        tot += lens[i];
+    }
+    r->codes.resize((size_t)tot);
+    r->off.resize((size_t)n);
+    r->lens.assign(lens, lens + n);
+    tot = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t c = 0; c < lens[i]; ++c)
+            if (seqs[i][c] >= QP_ALPHA) {
+                delete r;
+                return qp::set_error(QP_EINVAL, "residue code out of range");
+            }
+        std::memcpy(r->codes.data() + tot, seqs[i], (size_t)lens[i]);
+        r->off[i] = tot;
+        tot += lens[i];
+    }
+    r->params = *params;
+    r->thresh = thresh;
+    for (int32_t i = 0; i + 1 < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j) r->cells += (int64_t)lens[i] * lens[j];
+    if (n >= 2) {
+        qp_status st = qp::plan_shape(r->lens.data(), n, nullptr, nullptr, 0, params, thresh, 0, s->wave_budget,
+                                      &r->plan);
+        if (st != QP_OK) {
+            delete r;
+            return st;
+        }
+        r->bytes = qp::plan_bytes(r->plan) + tot + 8 * (int64_t)n + 1024;
+        if (r->bytes > s->cfg.hbm_budget_bytes) {
+            const int64_t need = r->bytes;
+            qp_plan_destroy(r->plan);
+            delete r;
+            char msg[160];
+            std::snprintf(msg, sizeof(msg), "family needs %lld device bytes, more than the whole budget",
+                          (long long)need);
+            return qp::set_error(QP_ENOMEM, msg);
+        }
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) {
+        if (r->plan) qp_plan_destroy(r->plan);
+        delete r;
+        return qp::set_error(QP_ECANCELED, "server is shutting down");
+    }
+    r->ticket = s->next_ticket++;
+    s->all[r->ticket] = r;
+    if (n < 2) {
+        // nothing to compute: an immediately finished, empty result
+        r->result = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
+        if (r->result) {
+            r->result->n_seqs = n;
+            r->result->row_off = (int64_t*)std::calloc(1, sizeof(int64_t));
+            r->result->nnz_off = (int64_t*)std::calloc(1, sizeof(int64_t));
+        }
+        r->state = St::Done;
+        r->t_admit = r->t_done = now_s();
+        s->finished++;
+        s->cv_done.notify_all();
+    } else {
+        s->queue.push_back(r);
+        s->cv_work.notify_all();
+    }
+    *ticket = r->ticket;
+    return QP_OK;
 }
-qp_status qp_server_wait(qp_server*, uint64_t, int32_t, qp_result** out, qp_request_times*) {
+
+qp_status qp_server_wait(qp_server* s, uint64_t ticket, int32_t timeout_ms, qp_result** out,
+                         qp_request_times* times) {
     if (out) *out = nullptr;
-    return QP_EINVAL;
+    if (!s || !out) return qp::set_error(QP_EINVAL, "server or out is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return qp::set_error(QP_EINVAL, "unknown ticket");
+    Request* r = it->second;
+    auto ready = [&] { return r->state == St::Done || r->state == St::Canceled; };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+        return qp::set_error(timeout_ms == 0 ? QP_EBUSY : QP_ETIMEDOUT, "result not ready");
+    s->all.erase(it);
+    if (times) {
+        times->submit_s = r->t_submit;
+        times->admit_s = r->t_admit;
+        times->done_s = r->t_done;
+        times->cells = r->cells;
+    }
+    qp_status st = r->status;
+    if (r->state == St::Canceled) st = QP_ECANCELED;
+    if (st == QP_OK) {
+        *out = r->result;
+        r->result = nullptr;
+    } else {
+        qp::set_error(st, r->error.empty() ? "request failed" : r->error.c_str());
+    }
+    if (r->result) qp_result_free(r->result);
+    delete r;
+    return st;
 }
-qp_status qp_server_cancel(qp_server*, uint64_t) { return QP_EINVAL; }
-qp_status qp_server_stats(qp_server*, int64_t*, int64_t*, int64_t*, int64_t*) { return QP_EINVAL; }
-qp_status qp_server_destroy(qp_server*) { return QP_EINVAL; }
+
+qp_status qp_server_cancel(qp_server* s, uint64_t ticket) {
+    if (!s) return qp::set_error(QP_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return qp::set_error(QP_EINVAL, "unknown ticket");
+    Request* r = it->second;
+    if (r->state != St::Queued) return qp::set_error(QP_EBUSY, "request already admitted");
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+    if (r->plan) qp_plan_destroy(r->plan);
+    r->plan = nullptr;
+    r->state = St::Canceled;
+    r->t_done = now_s();
+    s->cv_done.notify_all();
+    return QP_OK;
 }
+
+qp_status qp_server_stats(qp_server* s, int64_t* queued, int64_t* in_flight, int64_t* finished,
+                          int64_t* bytes_in_use) {
+    if (!s) return qp::set_error(QP_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(s->mu);
+    if (queued) *queued = (int64_t)s->queue.size();
+    if (in_flight) *in_flight = (int64_t)s->running.size();
+    if (finished) *finished = s->finished;
+    if (bytes_in_use) *bytes_in_use = s->bytes_in_use;
+    return QP_OK;
+}
+
+qp_status qp_server_destroy(qp_server* s) {
+    if (!s) return QP_OK;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        // pending requests are cancelled; running ones finish
+        for (Request* r : s->queue) {
+            if (r->plan) qp_plan_destroy(r->plan);
+            r->plan = nullptr;
+            r->state = St::Canceled;
+        }
+        s->queue.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    if (s->thr.joinable()) s->thr.join();
+    for (auto& kv : s->all) {
+        if (kv.second->result) qp_result_free(kv.second->result);
+        release_device(kv.second);
+        delete kv.second;
+    }
+    for (hipStream_t st : s->streams) hipStreamDestroy(st);
+    delete s;
+    return QP_OK;
+}
+
+}  // extern "C"

@@ -117,3 +117,10 @@ def test_no_device_is_reported(B, params):
 def test_result_free_null_safe(B):
     B.lib.qp_result_free(None)
     B.lib.qp_plan_destroy(None)
+
+
+def test_server_config_errors(B):
+    for cfg in [(0, 4, 2), (1 << 30, 0, 2), (1 << 30, 65, 2), (1 << 30, 4, 0), (1 << 30, 4, 17)]:
+        with pytest.raises(B.QpError) as e:
+            B.Server(*cfg)
+        assert e.value.status in (B.QP_EINVAL, B.QP_EDEVICE)

@@ -1,0 +1,97 @@
+"""Serving loop on the GPU: continuous batching gives each family exactly the
+result it gets alone; admission respects the device-memory budget."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1512_07437_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1512_07437_amd import binding
+    return binding
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _families():
+    rng = np.random.default_rng(40)
+    fams = []
+    for f in range(6):
+        k = int(rng.integers(3, 14))
+        lens = rng.integers(60, 420, size=k)
+        fams.append(W.make_family(k, lens, 1000 + f, r_sub=0.3, r_indel=0.05))
+    return fams
+
+
+KEYS = ("pair_i", "pair_j", "row_off", "row_ptr", "nnz_off", "col", "val", "dist", "log_z")
+
+
+def test_alone_equals_mix(B, params):
+    p = B.make_params(params)
+    fams = _families()
+    _say("serving: alone")
+    alone = [B.qp_posteriors(f, p, 0.01) for f in fams]
+    _say("serving: mix")
+    srv = B.Server(hbm_budget_bytes=64 << 30, max_slots=4, n_streams=3)
+    try:
+        tickets = [srv.submit(f, p, 0.01) for f in fams]
+        got = [srv.wait(t, timeout_ms=60000) for t in tickets]
+    finally:
+        srv.close()
+    for a, (r, tm) in zip(alone, got):
+        for key in KEYS:
+            assert np.array_equal(a[key], r[key]), key
+        assert tm["submit_s"] <= tm["admit_s"] <= tm["done_s"]
+
+
+def test_budget_admission(B, params):
+    p = B.make_params(params)
+    fams = _families()[:3]
+    # a budget too small for any family is rejected at submit
+    srv = B.Server(hbm_budget_bytes=1 << 20, max_slots=2, n_streams=2)
+    try:
+        with pytest.raises(B.QpError) as e:
+            srv.submit(fams[0], p, 0.01)
+        assert e.value.status == B.QP_ENOMEM
+    finally:
+        srv.close()
+    # one slot: families run one after the other, in arrival order
+    _say("serving: one slot")
+    srv = B.Server(hbm_budget_bytes=64 << 30, max_slots=1, n_streams=2)
+    try:
+        ts = [srv.submit(f, p, 0.01) for f in fams]
+        times = [srv.wait(t, timeout_ms=60000)[1] for t in ts]
+        for a, b in zip(times, times[1:]):
+            assert b["admit_s"] >= a["done_s"] - 1e-3
+        assert srv.stats()["finished"] == 3
+    finally:
+        srv.close()
+
+
+def test_cancel_and_poll(B, params):
+    p = B.make_params(params)
+    fams = _families()
+    srv = B.Server(hbm_budget_bytes=64 << 30, max_slots=1, n_streams=1)
+    try:
+        ts = [srv.submit(f, p, 0.01) for f in fams[:4]]
+        # the last one is still queued behind a single slot
+        st = srv.cancel(ts[-1])
+        assert st in (B.QP_OK, B.QP_EBUSY)
+        with pytest.raises(B.QpError):
+            srv.wait(99999, timeout_ms=0)
+        for t in ts[:-1]:
+            srv.wait(t, timeout_ms=60000)
+        if st == B.QP_OK:
+            with pytest.raises(B.QpError) as e:
+                srv.wait(ts[-1], timeout_ms=1000)
+            assert e.value.status == B.QP_ECANCELED
+    finally:
+        srv.close()
