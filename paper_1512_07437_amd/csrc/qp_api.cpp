@@ -213,7 +213,7 @@ void size_slot(const qp_plan* pl, qp_plan::ClassPlan* c) {
     const int64_t v2 = pl->fp64 ? 16 : 8;
     const int64_t steps = (int64_t)c->nmax + qp::kWave - 1;
     a.spill_band_stride = steps * qp::kWave * c->R;
-    a.exps_band_stride = steps * qp::kWave;
+    a.exps_band_stride = ((steps + qp::kRescaleEvery - 1) / qp::kRescaleEvery) * qp::kWave;
     a.bnd_stride = c->nmax + 2;
     int64_t off = align256(c->nb_max * a.spill_band_stride * v2);
     a.off_exps = off;
@@ -679,6 +679,7 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
     }
     pl->args.seqs = d_seqs;
     pl->args.seq_off = d_seq_off;
+    set_class_args(pl);  // the class launches carry their own copy of the arguments
     pl->last_stream = s;
     pl->ran = true;
     if (pl->P == 0) return QP_OK;

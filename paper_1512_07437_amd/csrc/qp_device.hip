@@ -250,7 +250,11 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 st.y = ngM;
                 sp[r * kWave + lane] = st;
             }
-            (exps + (int64_t)s * kWave)[lane] = make_int2(EH, EP);
+            // exponents change only at the rescale after every kRescaleEvery-th
+            // step: one record per block (written at the block's first step,
+            // or at the lane's first column if that comes later)
+            if ((s % kRescaleEvery) == 0 || j == 1)
+                (exps + (int64_t)(s / kRescaleEvery) * kWave)[lane] = make_int2(EH, EP);
             oM = upM; oU1 = upU1; oU2 = upU2;
             ogM = gupM; ogU = gupU;
             if (!last && lane == L - 1) {
@@ -362,7 +366,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         const V2* sp = spill + (int64_t)(S - 1) * R * kWave;
 #pragma unroll
         for (int r = 0; r < R; ++r) fa[r] = sp[r * kWave + lane];
-        ea = (exps + (int64_t)(S - 1) * kWave)[lane];
+        ea = (exps + (int64_t)((S - 1) / kRescaleEvery) * kWave)[lane];
     }
     BwdBnd<T> bq;  // lane L-1 of an upper band: boundary record of its next column
     if (!LAST && lane == L - 1) bq = bin[n];
@@ -382,7 +386,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             const V2* sp = spill + (int64_t)tn * R * kWave;
 #pragma unroll
             for (int r = 0; r < R; ++r) fn[r] = sp[r * kWave + lane];
-            en = (exps + (int64_t)tn * kWave)[lane];
+            en = (exps + (int64_t)(tn / kRescaleEvery) * kWave)[lane];
         }
         // ---- exchange with the lane below
         T rU1 = dpp<kDppWaveShl1>(oU1), rU2 = dpp<kDppWaveShl1>(oU2), rT = dpp<kDppWaveShl1>(Tp[0]);
@@ -412,6 +416,18 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             if (edge) bq = bin[j - 1 >= 1 ? j - 1 : 1];
         }
         {
+            // A lane that has not started yet (and the first step of it)
+            // holds no state except the diagonal input; it takes over the
+            // exponent of the values flowing in, so that nothing is converted
+            // across a large exponent gap (right-edge values far above the
+            // last row are ~eps^(m-i) and would underflow in FP32).  The lane
+            // holding the end state keeps its own scale.
+            const bool adopt = j >= n && !(LAST && lane == L - 1);
+            const int nFH = adopt ? rFH : FH, nFP = adopt ? rFP : FP;
+            bT = qldexp(bT, FH - nFH);
+            bgT = qldexp(bgT, FP - nFP);
+            FH = nFH;
+            FP = nFP;
             const int dH = rFH - FH, dP = rFP - FP;
             rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rT = qldexp(rT, dH);
             rgU = qldexp(rgU, dP); rgT = qldexp(rgT, dP);
@@ -441,15 +457,15 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 const T P = pH + pP;
                 const double nA = fmax(dgA + (double)P, fmax(dA, A[r]));
                 const int row = lane * R + r;
-                if (P >= (T)thresh && row < rows) {
-                    const int c = cnt[r];
-                    if (c < cap) {
-                        const uint32_t at = (uint32_t)(r0 + row) * (uint32_t)cap + (uint32_t)c;
-                        stage_col[at] = j - 1;
-                        stage_val[at] = (float)P;
-                    }
-                    cnt[r] = c + 1;
+                // one branch per row; a row that overflows its staging keeps
+                // overwriting its last slot and is reported after the pass
+                const bool hit = P >= (T)thresh && row < rows;
+                if (hit) {
+                    const uint32_t at = (uint32_t)(r0 + row) * (uint32_t)cap + (uint32_t)min(cnt[r], cap - 1);
+                    stage_col[at] = j - 1;
+                    stage_val[at] = (float)P;
                 }
+                cnt[r] += hit ? 1 : 0;
                 dgT = Tp[r]; dggT = gTp[r]; dgA = A[r];
                 Tp[r] = nT; gTp[r] = ngT; A[r] = nA;
                 bV1[r] = nV1; bV2[r] = nV2; gbV[r] = ngV;
@@ -598,7 +614,10 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
         a.logz[2 * p + 1] = lzp;
         a.dist[p] = 1.0 - a11 / (double)min(m, n);
     }
-    if ((int64_t)base + nnz > a.pool_cap) {
+    // counts are written by the backward pass and bounded by cap, so a
+    // negative total cannot occur on a complete pass; it is refused anyway,
+    // since a wrapped total would pass the capacity test below
+    if (nnz < 0 || (int64_t)base + nnz > a.pool_cap) {
         if (lane == 0) atomicOr(a.flags, 1);
         return;
     }

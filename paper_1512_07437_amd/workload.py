@@ -102,36 +102,41 @@ def substitution_matrix(seed: int = 0) -> np.ndarray:
 # --------------------------------------------------------------------------
 # evolution model
 # --------------------------------------------------------------------------
-def _geom_len(rng: np.random.Generator) -> int:
-    # Geometric on {1,2,...} with success probability 1/3 (mean 3)
-    return int(rng.geometric(1.0 / 3.0))
-
-
 def evolve(root: np.ndarray, rng: np.random.Generator, q: np.ndarray, subst: np.ndarray,
            r_sub: float, r_indel: float) -> np.ndarray:
     """One leaf of a star tree.  Per root site: substitute with probability
     ``r_sub`` (new residue from the substitution row), then with probability
-    ``r_indel`` open an indel: half the time delete the following run of sites,
-    otherwise insert a run of background residues; run lengths are geometric
-    with mean 3."""
-    out: List[int] = []
-    i = 0
+    ``r_indel`` open an indel after it: half the time delete the following run
+    of sites, otherwise insert a run of background residues; run lengths are
+    geometric with mean 3.  Deleted sites are skipped together with any indel
+    they would have opened."""
     L = len(root)
+    root = np.asarray(root, dtype=np.int64)
+    # substitutions (inverse-CDF draw from the row of the old residue)
     cdf = np.cumsum(subst, axis=1)
-    while i < L:
-        a = int(root[i])
-        if rng.random() < r_sub:
-            a = int(np.searchsorted(cdf[a], rng.random() * cdf[a, -1], side="right"))
-            a = min(a, K - 1)
-        out.append(a)
-        i += 1
-        if rng.random() < r_indel:
-            g = _geom_len(rng)
-            if rng.random() < 0.5:
-                i += g  # deletion of the next g root sites
-            else:
-                out.extend(int(c) for c in rng.choice(K, size=g, p=q))
-    return np.asarray(out, dtype=np.uint8)
+    cdf /= cdf[:, -1:]
+    sub = rng.random(L) < r_sub
+    u = rng.random(L)
+    new = (cdf[root] > u[:, None]).argmax(axis=1)
+    site = np.where(sub, new, root)
+    # indel events after each site
+    ev = rng.random(L) < r_indel
+    kind_del = rng.random(L) < 0.5
+    glen = rng.geometric(1.0 / 3.0, size=L)
+    out: List[np.ndarray] = []
+    i = 0
+    for e in np.flatnonzero(ev):
+        if e < i:
+            continue  # inside a deletion
+        out.append(site[i:e + 1])
+        if kind_del[e]:
+            i = e + 1 + int(glen[e])
+        else:
+            out.append(rng.choice(K, size=int(glen[e]), p=q))
+            i = e + 1
+    if i < L:
+        out.append(site[i:])
+    return (np.concatenate(out) if out else np.zeros(0, np.int64)).astype(np.uint8)
 
 
 def fit_length(seq: np.ndarray, target: int, rng: np.random.Generator, q: np.ndarray) -> np.ndarray:
