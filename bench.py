@@ -36,6 +36,35 @@ METRIC = "all-pairs posterior GCUPS & pairs/s at ≤1e-5 vs FP64 oracle; p99 fam
 FLOP_PER_CELL = 67.0
 FP32_VALU_PEAK_TFLOPS = 157.3
 FP64_VALU_PEAK_TFLOPS = 78.6
+KERNEL_SRC = os.path.join(ROOT, "paper_1512_07437_amd", "csrc", "qp_device.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_hbm_traffic.txt")
+
+
+def kernel_name(cls: int, fp64: bool) -> str:
+    """Symbol of the persistent pair kernel of one class, as profilers print it."""
+    r = cls + 1 if cls < 8 else 8
+    return "qp::k_pairs<%d, %s, %s>" % (r, "double" if fp64 else "float", "true" if cls == 8 else "false")
+
+
+def committed_traffic(kernel: str, workload_key: str):
+    """HBM bytes per launch (read, write) of `kernel` on `workload_key` from the
+    committed counter summary, or None when the summary is missing or was
+    taken on a different kernel source than the one built now."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_FILE).read().splitlines()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    src = [ln.split("=", 1)[1].strip() for ln in text if ln.startswith("source_sha256")]
+    if not src or src[0] != sha:
+        return None
+    for ln in text:
+        f = ln.split("\t")
+        if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[2] == workload_key:
+            return float(f[3]), float(f[4])
+    return None
 
 
 def workload(name: str):
@@ -168,7 +197,19 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     gcups = cells / (dt / args.steps) / 1e9
     peak = FP64_VALU_PEAK_TFLOPS if prec == B.QP_FP64 else FP32_VALU_PEAK_TFLOPS
-    achieved = cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12 if kernel_ms > 0 else None
+    fp64 = prec == B.QP_FP64
+    # per-class pair kernels (run concurrently); the dominant one is the
+    # class with the longest average launch
+    classes = []
+    for c in range(9):
+        c_ms, c_pairs, c_cells, c_r = plan.class_timing(c)
+        if c_pairs:
+            classes.append({"class": c, "kernel": kernel_name(c, fp64), "rows_per_lane": c_r, "pairs": c_pairs,
+                            "cells": c_cells, "avg_ms": round(c_ms, 4),
+                            "tflops": round(c_cells * FLOP_PER_CELL / (c_ms * 1e-3) / 1e12, 3) if c_ms > 0 else None})
+    dom = max(classes, key=lambda r: r["avg_ms"]) if classes else None
+    achieved = dom["tflops"] if dom else None
+    traffic = committed_traffic(dom["kernel"], args.workload + ("_fp64" if fp64 else "")) if dom else None
     out = {
         "metric": METRIC,
         "value": round(gcups, 3),
@@ -187,10 +228,13 @@ def main():
         "pairs_per_s": round(n_pairs / (dt / args.steps), 1),
         "kernel_ms": round(kernel_ms, 4),
         "pipeline_ms": round(pipe_ms, 4),
-        "roofline": {"bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
-                     "peak": peak, "unit": "TFLOP/s",
+        "roofline": {"bound": "alu", "kernel": dom["kernel"] if dom else None,
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": None if achieved is None else round(achieved / peak, 4),
-                     "traffic": None},
+                     "traffic": None if traffic is None else traffic[0] + traffic[1],
+                     "traffic_read_write": None if traffic is None else [traffic[0], traffic[1]]},
+        "pair_kernels": classes,
+        "all_classes_tflops": round(cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12, 3) if kernel_ms > 0 else None,
     }
     if not args.no_cpu and sample is not None:
         c_cells, c_dt, worst, ea_worst = cpu_baseline(fam, pairs, sample, mp, res, len(fam))

@@ -214,6 +214,17 @@ qp_status qp_plan_download(qp_plan* plan, qp_result** out);
  * the run stream; *n_runs receives the number of runs averaged. */
 qp_status qp_plan_timing(qp_plan* plan, double* kernel_ms, double* pipeline_ms, int64_t* n_runs, int32_t reset);
 
+/* One kernel class of the plan (0..8): pairs whose row sequence needs
+ * *rows_per_lane rows per lane of a 64-lane wavefront (classes 0..7: R =
+ * 1..8, one band of 64R rows; class 8: R = 8 in several bands).  *pairs and
+ * *cells are the pairs and m*n cells of this family in the class (0 when it
+ * is absent); *kernel_ms is the average duration of the class's persistent
+ * kernel over the timed runs (events recorded on the stream it runs on;
+ * reset together with qp_plan_timing).  Any output pointer may be NULL.
+ * QP_EINVAL for a class outside [0, 9). */
+qp_status qp_plan_class_timing(qp_plan* plan, int32_t cls, double* kernel_ms, int64_t* pairs, int64_t* cells,
+                               int32_t* rows_per_lane);
+
 /* Use (1) or stop using (0) the captured HIP graph for subsequent runs
  * (default 1). */
 qp_status qp_plan_set_graph(qp_plan* plan, int32_t use_graph);

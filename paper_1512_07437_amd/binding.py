@@ -83,6 +83,8 @@ SIGNATURES = {
     "qp_plan_download": (ctypes.c_int, [ctypes.c_void_p, _P(_P(qp_result))]),
     "qp_plan_timing": (ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), _P(ctypes.c_double),
                                       _P(ctypes.c_int64), ctypes.c_int32]),
+    "qp_plan_class_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double),
+                                            _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_int32)]),
     "qp_plan_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "qp_plan_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
     "qp_plan_destroy": (None, [ctypes.c_void_p]),
@@ -221,8 +223,14 @@ def pair_dense(res: Dict[str, np.ndarray], p: int, n_cols: int) -> np.ndarray:
 
 
 class Plan:
-    """Device-resident plan (qp_plan_*): inputs are torch tensors on the GPU,
-    the stream is torch's; outputs stay on the device until downloaded."""
+    """Device-resident plan (qp_plan_*): inputs are device buffers (torch
+    tensors or hipMalloc'd memory), the stream any HIP stream; outputs stay on
+    the device until downloaded.
+
+    torch bundles its own HIP runtime; when torch and this library share a
+    process, let torch initialize the GPU first (e.g. allocate a tensor before
+    loading this module): torch's runtime does not initialize after another
+    one has."""
 
     def __init__(self, lens: Sequence[int], params: qp_params, thresh: float, pair_i=None, pair_j=None,
                  nnz_capacity: int = 0):
@@ -267,6 +275,13 @@ class Plan:
         k, p, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
         _check(lib.qp_plan_timing(self.handle, ctypes.byref(k), ctypes.byref(p), ctypes.byref(n), int(reset)))
         return k.value, p.value, n.value
+
+    def class_timing(self, cls: int):
+        """(kernel_ms, pairs, cells, rows_per_lane) of one kernel class."""
+        k, p, c, r = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.qp_plan_class_timing(self.handle, int(cls), ctypes.byref(k), ctypes.byref(p), ctypes.byref(c),
+                                        ctypes.byref(r)))
+        return k.value, p.value, c.value, r.value
 
     def set_graph(self, on: bool):
         _check(lib.qp_plan_set_graph(self.handle, int(on)))

@@ -129,6 +129,13 @@ struct qp_plan {
     void* d_col0 = nullptr;
     qp::DevConsts* d_consts = nullptr;
     int32_t* d_lens = nullptr;
+    // 4-byte aligned, padded copy of the family's residues (the kernels read
+    // one sequence per pair through the scalar cache in whole dwords)
+    uint8_t* d_seqa = nullptr;
+    int64_t* d_seqa_off = nullptr;
+    std::vector<int64_t> seqa_off;
+    const uint8_t* in_seqs = nullptr;
+    const int64_t* in_off = nullptr;
     int32_t* d_list_i = nullptr;
     int32_t* d_list_j = nullptr;
     int32_t* d_pi = nullptr;
@@ -157,9 +164,12 @@ struct qp_plan {
     const void* cap_seqs = nullptr;
     const void* cap_off = nullptr;
     hipEvent_t ev[kNumEventSets][4] = {};
+    // start / end of each class kernel, recorded on the stream it runs on
+    hipEvent_t cev[kNumEventSets][qp::kClasses][2] = {};
     bool ev_pending[kNumEventSets] = {};
     int run_idx = 0;
     double sum_kernel_ms = 0.0, sum_pipe_ms = 0.0;
+    double sum_class_ms[qp::kClasses] = {};
     int64_t n_timed = 0;
     hipStream_t last_stream = nullptr;
     bool ran = false;
@@ -222,10 +232,9 @@ void size_slot(const qp_plan* pl, qp_plan::ClassPlan* c) {
     off += align256(2 * a.bnd_stride * (int64_t)qp::fwd_bnd_bytes(pl->fp64));
     a.off_bb = off;
     off += align256(2 * a.bnd_stride * (int64_t)qp::bwd_bnd_bytes(pl->fp64));
-    a.off_stage_col = off;
-    off += align256((int64_t)c->mmax * c->cap * 4);
-    a.off_stage_val = off;
-    off += align256((int64_t)c->mmax * c->cap * 4);
+    // hit log: at most cap records of 16 bytes per row
+    a.off_log = off;
+    off += align256((int64_t)c->mmax * c->cap * 16);
     a.slot_bytes = off;
 }
 
@@ -244,8 +253,7 @@ static void set_class_args(qp_plan* pl) {
         a.off_exps = cp.args.off_exps;
         a.off_fb = cp.args.off_fb;
         a.off_bb = cp.args.off_bb;
-        a.off_stage_col = cp.args.off_stage_col;
-        a.off_stage_val = cp.args.off_stage_val;
+        a.off_log = cp.args.off_log;
         a.spill_band_stride = cp.args.spill_band_stride;
         a.exps_band_stride = cp.args.exps_band_stride;
         a.bnd_stride = cp.args.bnd_stride;
@@ -273,6 +281,10 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     }
     ALLOC(pl->d_consts, 1);
     ALLOC(pl->d_lens, pl->n);
+    pl->seqa_off.assign((size_t)pl->n + 1, 0);
+    for (int32_t i = 0; i < pl->n; ++i) pl->seqa_off[i + 1] = pl->seqa_off[i] + ((pl->lens[i] + 3) & ~3);
+    ALLOC(pl->d_seqa, pl->seqa_off[pl->n] + 4);
+    ALLOC(pl->d_seqa_off, pl->n + 1);
     if (!pl->all_pairs) {
         ALLOC(pl->d_list_i, P);
         ALLOC(pl->d_list_j, P);
@@ -301,6 +313,7 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
 #undef ALLOC
     if (dry) return QP_OK;
     HIP_TRY(hipMemcpy(pl->d_lens, pl->lens.data(), sizeof(int32_t) * pl->n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(pl->d_seqa_off, pl->seqa_off.data(), sizeof(int64_t) * (pl->n + 1), hipMemcpyHostToDevice));
     if (!pl->all_pairs) {
         HIP_TRY(hipMemcpy(pl->d_list_i, pl->list_i.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(pl->d_list_j, pl->list_j.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
@@ -321,6 +334,8 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
 
     qp::PairArgs& a = pl->args;
     a.lens = pl->d_lens;
+    a.seqs = pl->d_seqa;
+    a.seq_off = pl->d_seqa_off;
     a.pair_i = pl->d_pi;
     a.pair_j = pl->d_pj;
     a.queue = pl->d_queue;
@@ -354,10 +369,13 @@ static hipError_t record(hipEvent_t e, hipStream_t s, bool capturing) {
 }
 
 // enqueue every step of the pipeline on s; events optional
-static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, hipEvent_t* ev, bool capturing = false) {
+static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool capturing = false) {
     const int64_t P = pl->P;
+    hipEvent_t* ev = ev_set >= 0 ? pl->ev[ev_set] : nullptr;
     if (ev) HIP_TRY(record(ev[0], s, capturing));
     HIP_TRY(qp::launch_reset(pl->d_ints, pl->n_ints, s));
+    HIP_TRY(qp::launch_stage_seqs(pl->n, pl->in_seqs, pl->in_off, pl->d_lens, pl->d_seqa_off, pl->d_seqa,
+                                  pl->d_ints + kIntFlags, s));
     HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->d_col0, pl->mmax, pl->fp64, s));
     HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
                              pl->d_key, pl->d_ints + kIntHist, pl->d_nnz, s));
@@ -369,17 +387,22 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, hipEvent_t* ev, bo
     int present[qp::kClasses], np = 0;
     for (int c = qp::kClasses - 1; c >= 0; --c)
         if (pl->cls[c].grid > 0) present[np++] = c;
+    auto launch_class = [&](int c, hipStream_t cs) -> qp_status {
+        if (ev) HIP_TRY(record(pl->cev[ev_set][c][0], cs, capturing));
+        HIP_TRY(qp::launch_pairs(c, pl->fp64, pl->cls[c].grid, pl->cls[c].args, cs));
+        if (ev) HIP_TRY(record(pl->cev[ev_set][c][1], cs, capturing));
+        return QP_OK;
+    };
+    qp_status cst;
     if (np == 1 || pl->n_side == 0) {
         for (int q = 0; q < np; ++q)
-            HIP_TRY(qp::launch_pairs(present[q], pl->fp64, pl->cls[present[q]].grid, pl->cls[present[q]].args, s));
+            if ((cst = launch_class(present[q], s)) != QP_OK) return cst;
     } else {
         HIP_TRY(hipEventRecord(pl->fork_ev, s));
         const int ns = std::min(np, pl->n_side);
         for (int q = 0; q < ns; ++q) HIP_TRY(hipStreamWaitEvent(pl->side[q], pl->fork_ev, 0));
-        for (int q = 0; q < np; ++q) {
-            const int c = present[q];
-            HIP_TRY(qp::launch_pairs(c, pl->fp64, pl->cls[c].grid, pl->cls[c].args, pl->side[q % ns]));
-        }
+        for (int q = 0; q < np; ++q)
+            if ((cst = launch_class(present[q], pl->side[q % ns])) != QP_OK) return cst;
         for (int q = 0; q < ns; ++q) {
             HIP_TRY(hipEventRecord(pl->join_ev[q], pl->side[q]));
             HIP_TRY(hipStreamWaitEvent(s, pl->join_ev[q], 0));
@@ -404,7 +427,7 @@ static qp_status capture_graphs(qp_plan* pl) {
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return fail(QP_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
-        qp_status st = enqueue_pipeline(pl, pl->cap_stream, pl->ev[g], true);
+        qp_status st = enqueue_pipeline(pl, pl->cap_stream, g, true);
         e = hipStreamEndCapture(pl->cap_stream, &graph);
         if (st != QP_OK) {
             if (graph) hipGraphDestroy(graph);
@@ -427,6 +450,12 @@ static void collect_timing(qp_plan* pl) {
             pl->sum_kernel_ms += k;
             pl->sum_pipe_ms += p;
             pl->n_timed += 1;
+            for (int c = 0; c < qp::kClasses; ++c) {
+                float ck = 0.f;
+                if (pl->cls[c].grid > 0 &&
+                    hipEventElapsedTime(&ck, pl->cev[g][c][0], pl->cev[g][c][1]) == hipSuccess)
+                    pl->sum_class_ms[c] += ck;
+            }
         } else {
             (void)hipGetLastError();
         }
@@ -622,8 +651,12 @@ qp_status qp::plan_materialize(qp_plan* pl) {
     }
     hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) {
-        for (int g = 0; g < kNumEventSets && e == hipSuccess; ++g)
+        for (int g = 0; g < kNumEventSets && e == hipSuccess; ++g) {
             for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipEventCreate(&pl->ev[g][q]);
+            for (int c = 0; c < qp::kClasses && e == hipSuccess; ++c)
+                if (pl->cls[c].grid > 0)
+                    for (int q = 0; q < 2 && e == hipSuccess; ++q) e = hipEventCreate(&pl->cev[g][c][q]);
+        }
     }
     int n_present = 0;
     for (int c = 0; c < qp::kClasses; ++c) n_present += pl->cls[c].grid > 0;
@@ -677,9 +710,8 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
         HIP_TRY(hipEventSynchronize(pl->ev[g][3]));
         collect_timing(pl);
     }
-    pl->args.seqs = d_seqs;
-    pl->args.seq_off = d_seq_off;
-    set_class_args(pl);  // the class launches carry their own copy of the arguments
+    pl->in_seqs = d_seqs;
+    pl->in_off = d_seq_off;
     pl->last_stream = s;
     pl->ran = true;
     if (pl->P == 0) return QP_OK;
@@ -706,7 +738,7 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
         }
     }
     trace("run: eager (event set %d)", g);
-    qp_status st = enqueue_pipeline(pl, s, pl->ev[g]);
+    qp_status st = enqueue_pipeline(pl, s, g);
     if (st != QP_OK) return st;
     pl->ev_pending[g] = true;
     pl->last_g = g;
@@ -733,6 +765,7 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
     }
     pl->last_nnz = nnz;
     trace("sync: done nnz=%lld flags=%d", (long long)nnz, flags);
+    if (flags & 4) return fail(QP_EINVAL, "a device sequence holds a residue code >= %d", QP_ALPHA);
     if (flags & 2)
         return fail(QP_EDEVICE, "a row held more entries above the threshold than its staging capacity");
     if ((flags & 1) || nnz > pl->pool_cap) {
@@ -851,7 +884,28 @@ qp_status qp_plan_timing(qp_plan* pl, double* kernel_ms, double* pipeline_ms, in
     if (n_runs) *n_runs = pl->n_timed;
     if (reset) {
         pl->sum_kernel_ms = pl->sum_pipe_ms = 0.0;
+        for (int c = 0; c < qp::kClasses; ++c) pl->sum_class_ms[c] = 0.0;
         pl->n_timed = 0;
+    }
+    return QP_OK;
+}
+
+qp_status qp_plan_class_timing(qp_plan* pl, int32_t cls, double* kernel_ms, int64_t* pairs, int64_t* cells,
+                               int32_t* rows_per_lane) {
+    if (!pl) return fail(QP_EINVAL, "plan is NULL");
+    if (cls < 0 || cls >= qp::kClasses) return fail(QP_EINVAL, "class %d outside [0, %d)", cls, qp::kClasses);
+    const qp_plan::ClassPlan& cp = pl->cls[cls];
+    if (pairs) *pairs = cp.grid > 0 ? cp.pairs : 0;
+    if (cells) *cells = cp.grid > 0 ? cp.cells : 0;
+    if (rows_per_lane) *rows_per_lane = qp::class_rows_per_lane(cls);
+    if (kernel_ms) {
+        *kernel_ms = 0.0;
+        if (cp.grid > 0 && pl->ran) {
+            HIP_TRY(hipSetDevice(pl->device));
+            if (pl->last_g >= 0) HIP_TRY(hipEventSynchronize(pl->ev[pl->last_g][3]));
+            collect_timing(pl);
+            *kernel_ms = pl->n_timed ? pl->sum_class_ms[cls] / pl->n_timed : 0.0;
+        }
     }
     return QP_OK;
 }
@@ -869,9 +923,13 @@ void qp_plan_destroy(qp_plan* pl) {
     hipSetDevice(pl->device);
     if (pl->ran && pl->last_g >= 0) hipEventSynchronize(pl->ev[pl->last_g][3]);
     plan_free_device(pl);
-    for (int g = 0; g < kNumEventSets; ++g)
+    for (int g = 0; g < kNumEventSets; ++g) {
         for (int q = 0; q < 4; ++q)
             if (pl->ev[g][q]) hipEventDestroy(pl->ev[g][q]);
+        for (int c = 0; c < qp::kClasses; ++c)
+            for (int q = 0; q < 2; ++q)
+                if (pl->cev[g][c][q]) hipEventDestroy(pl->cev[g][c][q]);
+    }
     if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
     for (int q = 0; q < 3; ++q) {
         if (pl->side[q]) hipStreamDestroy(pl->side[q]);

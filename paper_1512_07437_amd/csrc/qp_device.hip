@@ -107,6 +107,22 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
     return v;
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Residue idx of a sequence whose copy is 4-byte aligned and zero padded to
+// a multiple of 4 bytes: a uniform index makes this a scalar (SMEM) load, so
+// the step loops issue no vector loads for y and never wait on their stores.
+__device__ __forceinline__ int res_uniform(const uint8_t* y, int idx) {
+    typedef __attribute__((address_space(4))) const uint32_t cu32;
+    const uint64_t a = (uint64_t)(uintptr_t)y;
+    const cu32* w = (const cu32*)(uintptr_t)a;
+    return (int)((w[idx >> 2] >> ((idx & 3) * 8)) & 0xffu);
+}
+
 // ---------------------------------------------------------------- forward
 // One band of rows [r0, r0+rows) of pair (x, y); L lanes carry R rows each.
 template <int R, typename T, bool first, bool last>
@@ -189,14 +205,27 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     }
 
     const int S = n + L - 1;
-    int jn = 1 - lane;  // column of step 0
-    int ycur = (used && jn >= 1 && jn <= n) ? (int)y[jn - 1] : 0;
+    // residue of the lane's column: lane 0 reads y[s] (scalar), lane l takes
+    // lane l-1's residue of the previous step
+    int ycur = 0;
+    int y0n = res_uniform(y, 0);
     FwdBnd<T> bq;  // lane 0 of a lower band: boundary record of its next column
     if (!first && lane == 0) bq = fin[1];
+    // spill values of the current step; lanes outside their columns store
+    // stale values, so every store covers whole cache lines (a partial line
+    // costs a read-modify-write in HBM) and nothing reads them back
+    V2 sm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { sm[r].x = T(0); sm[r].y = T(0); }
     for (int s = 0; s < S; ++s) {
         const int j = s - lane + 1;
         const bool active = used && j >= 1 && j <= n;
-        const int ynext = (int)y[min(max(j, 0), n - 1)];  // clamped: read only when in range
+        {
+            const int y0 = y0n;
+            y0n = res_uniform(y, min(s + 1, n - 1));
+            const int yup = dpp_i<kDppWaveShr1>(ycur);
+            ycur = lane == 0 ? y0 : yup;
+        }
         // ---- exchange with the lane above
         T rM = dpp<kDppWaveShr1>(oM), rU1 = dpp<kDppWaveShr1>(oU1), rU2 = dpp<kDppWaveShr1>(oU2);
         T rD = dpp<kDppWaveShr1>(D[R - 1]), rgM = dpp<kDppWaveShr1>(ogM), rgU = dpp<kDppWaveShr1>(ogU);
@@ -225,7 +254,6 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         if (active) {
             T upM = rM, upU1 = rU1, upU2 = rU2, dg = aD;
             T gupM = rgM, gupU = rgU, gdg = gaD;
-            V2* sp = spill + (int64_t)s * R * kWave;  // uniform step base
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const V2 e = tab[xo[r] + ycur];
@@ -245,16 +273,9 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 gD[r] = ngD;
                 upM = nM; upU1 = nU1; upU2 = nU2;
                 gupM = ngM; gupU = ngU;
-                V2 st;
-                st.x = nM;
-                st.y = ngM;
-                sp[r * kWave + lane] = st;
+                sm[r].x = nM;
+                sm[r].y = ngM;
             }
-            // exponents change only at the rescale after every kRescaleEvery-th
-            // step: one record per block (written at the block's first step,
-            // or at the lane's first column if that comes later)
-            if ((s % kRescaleEvery) == 0 || j == 1)
-                (exps + (int64_t)(s / kRescaleEvery) * kWave)[lane] = make_int2(EH, EP);
             oM = upM; oU1 = upU1; oU2 = upU2;
             ogM = gupM; ogU = gupU;
             if (!last && lane == L - 1) {
@@ -265,9 +286,16 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 fout[j] = b;
             }
         }
+        {
+            V2* sp = spill + (int64_t)s * R * kWave;  // uniform step base
+#pragma unroll
+            for (int r = 0; r < R; ++r) sp[r * kWave + lane] = sm[r];
+        }
+        // exponents change only at the rescale closing every block of
+        // kRescaleEvery steps: one record per block, written by every lane
+        if ((s % kRescaleEvery) == 0) (exps + (int64_t)(s / kRescaleEvery) * kWave)[lane] = make_int2(EH, EP);
         aD = rD;
         gaD = rgD;
-        ycur = ynext;
         if ((s % kRescaleEvery) == kRescaleEvery - 1) {
             T mh = T(0), mp = T(0);
 #pragma unroll
@@ -311,8 +339,8 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                          int rows, int L, const typename Pair2<T>::type* tab, const Coef<T>& k,
                          const typename Pair2<T>::type* __restrict__ spill, const int2* __restrict__ exps,
                          const BwdBnd<T>* __restrict__ bin, BwdBnd<T>* __restrict__ bout, T invZH, T invZP, int ezH,
-                         int ezP, float thresh, int cap, int32_t* __restrict__ stage_col,
-                         float* __restrict__ stage_val, int32_t* __restrict__ rowcnt, int* __restrict__ flags,
+                         int ezP, float thresh, int cap, int4* __restrict__ hitlog, int& nlog,
+                         int32_t* __restrict__ rowcnt, int* __restrict__ flags,
                          double& a11) {
     using V2 = typename Pair2<T>::type;
     const bool used = lane < L;
@@ -338,12 +366,14 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     T bT = T(0), bgT = T(0);
     double bA = 0.0;
     if (LAST && lane == L - 1) {
-        // end state: the cell after (m, n) contributes weight 1 to (m, n)
+        // end state: the cell after (m, n) contributes weight w/Z to (m, n);
+        // every backward value is then already divided by Z (mantissa) and
+        // weighted, so the posterior is f * b times a power of two
         const int rm = (rows - 1) - (L - 1) * R;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (r == rm + 1) { Tp[r] = T(1); gTp[r] = T(1); }
-        if (rm + 1 == R) { bT = T(1); bgT = T(1); }
+            if (r == rm + 1) { Tp[r] = invZH; gTp[r] = invZP; }
+        if (rm + 1 == R) { bT = invZH; bgT = invZP; }
     }
     // vertical values of the strip's first row at the lane's current column,
     // handed to the lane above together with Tp[0], gTp[0], A[0] and FH, FP
@@ -351,11 +381,10 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
 
     const int S = n + L - 1;
     const int lead = L - 1 - lane;  // lane L-1 starts at column n
-    int ycur;
-    {
-        const int j0 = n + lead;
-        ycur = (used && j0 <= n) ? (int)y[j0 - 1] : 0;
-    }
+    // residue of the lane's column: lane L-1 reads y[n-1-t] (scalar), lane l
+    // takes lane l+1's residue of the previous step
+    int ycur = 0;
+    int yLn = res_uniform(y, n - 1);
     V2 fa[R], fb[R];
     int2 ea = make_int2(0, 0), eb = make_int2(0, 0);
 #pragma unroll
@@ -380,8 +409,12 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         // loads are straight-line and the wait for them is counted exactly;
         // lanes outside their columns never read what they loaded
         const int tn = t + 1 < S ? S - 2 - t : 0;
-        const int yi = min(max(j - 2, 0), n - 1);
-        const int ynext = (int)y[yi];
+        {
+            const int yl = yLn;
+            yLn = res_uniform(y, max(n - t - 2, 0));
+            const int ydn = dpp_i<kDppWaveShl1>(ycur);
+            ycur = lane == L - 1 ? yl : ydn;
+        }
         {
             const V2* sp = spill + (int64_t)tn * R * kWave;
 #pragma unroll
@@ -432,6 +465,8 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rT = qldexp(rT, dH);
             rgU = qldexp(rgU, dP); rgT = qldexp(rgT, dP);
         }
+        int hbits = 0;  // rows of this step at or above the threshold
+        float pv[R];    // and their posteriors
         if (active) {
             T dU1 = rU1, dU2 = rU2, dgU = rgU;
             double dA = rA;
@@ -452,19 +487,14 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 const T ngV = fma(k.u, gbV[r], tg);
                 const T gbM = fma(k.o, dgU + gbV[r], tg);
                 const T ngT = e.y * gbM;
-                const T pH = qldexp(fc[r].x * bM * invZH, kH);
-                const T pP = qldexp(fc[r].y * gbM * invZP, kP);
+                const T pH = qldexp(fc[r].x * bM, kH);
+                const T pP = qldexp(fc[r].y * gbM, kP);
                 const T P = pH + pP;
                 const double nA = fmax(dgA + (double)P, fmax(dA, A[r]));
                 const int row = lane * R + r;
-                // one branch per row; a row that overflows its staging keeps
-                // overwriting its last slot and is reported after the pass
                 const bool hit = P >= (T)thresh && row < rows;
-                if (hit) {
-                    const uint32_t at = (uint32_t)(r0 + row) * (uint32_t)cap + (uint32_t)min(cnt[r], cap - 1);
-                    stage_col[at] = j - 1;
-                    stage_val[at] = (float)P;
-                }
+                pv[r] = (float)P;
+                hbits |= hit ? (1 << r) : 0;
                 cnt[r] += hit ? 1 : 0;
                 dgT = Tp[r]; dggT = gTp[r]; dgA = A[r];
                 Tp[r] = nT; gTp[r] = ngT; A[r] = nA;
@@ -479,10 +509,25 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                 bout[j] = b;
             }
         }
+        // append this step's hits to the hit log, one contiguous run per row
+        // index across the wave (whole lines fill up in cache instead of
+        // sparse 4-byte writes); record = (row, rank from the row's end,
+        // column, value).  Uniform control flow keeps the log position in a
+        // scalar; a row past its capacity keeps counting and is reported.
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool keep = ((hbits >> r) & 1) != 0 && cnt[r] <= cap;
+            const unsigned long long km = __ballot(keep);
+            if (km) {
+                const int rank =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0));
+                if (keep) hitlog[nlog + rank] = make_int4(r0 + lane * R + r, cnt[r] - 1, j - 1, __float_as_int(pv[r]));
+                nlog = __builtin_amdgcn_readfirstlane(nlog + __popcll(km));
+            }
+        }
         bT = rT;
         bgT = rgT;
         bA = rA;
-        ycur = ynext;
         if ((t % kRescaleEvery) == kRescaleEvery - 1) {
             T mh = T(0), mp = T(0);
 #pragma unroll
@@ -502,12 +547,16 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             FP -= sp;
         }
     };
-    for (int t = 0; t < S; ++t) {
+    // two steps per trip, the prefetch buffers swapping roles, so the loads
+    // of one step are first waited for where the next step uses them
+    int t = 0;
+    for (; t + 1 < S; t += 2) {
         step(t, fa, ea, fb, eb);
-#pragma unroll
-        for (int r = 0; r < R; ++r) fa[r] = fb[r];
-        ea = eb;
+        __builtin_amdgcn_sched_barrier(0);
+        step(t + 1, fb, eb, fa, ea);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    if (t < S) step(t, fa, ea, fb, eb);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = lane * R + r;
@@ -532,16 +581,16 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
     const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
     const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
     const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
-    const uint8_t* x = a.seqs + a.seq_off[pi];
-    const uint8_t* y = a.seqs + a.seq_off[pj];
+    const uint8_t* x = a.seqs + uniform64(a.seq_off[pi]);
+    const uint8_t* y = a.seqs + uniform64(a.seq_off[pj]);
     const int H = kWave * R;
     const int nb = MULTI ? (m + H - 1) / H : 1;
     V2* spill = reinterpret_cast<V2*>(slot);
     int2* exps = reinterpret_cast<int2*>(slot + a.off_exps);
     FwdBnd<T>* fb = reinterpret_cast<FwdBnd<T>*>(slot + a.off_fb);
     BwdBnd<T>* bb = reinterpret_cast<BwdBnd<T>*>(slot + a.off_bb);
-    int32_t* stage_col = reinterpret_cast<int32_t*>(slot + a.off_stage_col);
-    float* stage_val = reinterpret_cast<float*>(slot + a.off_stage_val);
+    int4* hitlog = reinterpret_cast<int4*>(slot + a.off_log);
+    int nlog = 0;
 
     T zH = T(1), zP = T(1);
     int ezH = 0, ezP = 0;
@@ -578,7 +627,7 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
         BwdBnd<T>* bo = bb + (int64_t)(b & 1) * a.bnd_stride;
 #define QP_BWD(F, Lb)                                                                                      \
     bwd_band<R, T, F, Lb>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH, ezP, a.thresh, \
-                          a.cap, stage_col, stage_val, rp + 1, a.flags, a11)
+                          a.cap, hitlog, nlog, rp + 1, a.flags, a11)
         if (!MULTI)
             QP_BWD(true, true);
         else if (b == 0)
@@ -621,15 +670,14 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
         if (lane == 0) atomicOr(a.flags, 1);
         return;
     }
-    for (int row = lane; row < m; row += kWave) {
-        const int st = rp[row];
-        const int c = rp[row + 1] - st;
-        const int64_t dst0 = (int64_t)base + st + c - 1;
-        const int64_t src0 = (int64_t)row * a.cap;
-        for (int q = 0; q < c; ++q) {
-            a.pool_col[dst0 - q] = stage_col[src0 + q];
-            a.pool_val[dst0 - q] = stage_val[src0 + q];
-        }
+    // place the logged hits: the backward pass meets a row's columns in
+    // decreasing order, so rank k from the row's end lands at
+    // base + row_end - 1 - k (rows ascending, columns ascending)
+    for (int e = lane; e < nlog; e += kWave) {
+        const int4 h = hitlog[e];
+        const int64_t pos = (int64_t)base + rp[h.x + 1] - 1 - h.y;
+        a.pool_col[pos] = h.z;
+        a.pool_val[pos] = __int_as_float(h.w);
     }
     __threadfence_block();
 }
@@ -758,6 +806,24 @@ __global__ void k_reset(int* ints, int n) {
 }
 
 __device__ __forceinline__ int64_t pair_start(int64_t i, int64_t n) { return i * n - i * (i + 1) / 2; }
+
+// 4-byte aligned, zero padded copy of every sequence; codes outside 0..19
+// are reported through bit 4 of *flags (and copied as the padding code)
+__global__ void k_stage_seqs(int32_t n, const uint8_t* __restrict__ seqs, const int64_t* __restrict__ seq_off,
+                             const int32_t* __restrict__ lens, const int64_t* __restrict__ seqa_off,
+                             uint8_t* __restrict__ seqa, int* __restrict__ flags) {
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t src = seq_off[i], dst = seqa_off[i];
+        const int len = lens[i], padded = (int)(seqa_off[i + 1] - dst);
+        bool bad = false;
+        for (int c = threadIdx.x; c < padded; c += blockDim.x) {
+            const uint8_t v = c < len ? seqs[src + c] : (uint8_t)0;
+            bad |= v >= 20;
+            seqa[dst + c] = v >= 20 ? (uint8_t)kPadCode : v;  // keeps table reads in range
+        }
+        if (bad) atomicOr(flags, 4);
+    }
+}
 
 __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32_t* __restrict__ list_i,
                         const int32_t* __restrict__ list_j, int64_t P, int32_t* __restrict__ pi,
@@ -904,6 +970,14 @@ hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, c
     const int64_t blocks = (P + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, n, lens, list_i, list_j,
                        P, pi, pj, rows1, key, hist, pair_nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_seqs(int32_t n, const uint8_t* seqs, const int64_t* seq_off, const int32_t* lens,
+                             const int64_t* seqa_off, uint8_t* seqa, int* flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = n < 2048 ? n : 2048;
+    hipLaunchKernelGGL(k_stage_seqs, dim3(blocks), dim3(128), 0, s, n, seqs, seq_off, lens, seqa_off, seqa, flags);
     return hipGetLastError();
 }
 

@@ -82,13 +82,17 @@ struct PairArgs {
     // per-wave scratch slots
     char* scratch;
     int64_t slot_bytes;
-    int64_t off_exps, off_fb, off_bb, off_stage_col, off_stage_val;
+    int64_t off_exps, off_fb, off_bb, off_log;
     int64_t spill_band_stride;  // value pairs per band
     int64_t exps_band_stride;   // int2 per band
     int64_t bnd_stride;         // boundary records per buffer
 };
 
 // kernels launched by the host code (qp_device.hip)
+// copies each sequence to a 4-byte aligned slot of seqa (zero padded) and
+// sets bit 4 of *flags if a code is outside 0..19
+hipError_t launch_stage_seqs(int32_t n, const uint8_t* seqs, const int64_t* seq_off, const int32_t* lens,
+                             const int64_t* seqa_off, uint8_t* seqa, int* flags, hipStream_t s);
 hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, void* col0, int rows, int fp64,
                          hipStream_t s);
 size_t col0_bytes();

@@ -123,6 +123,12 @@ def evolve(root: np.ndarray, rng: np.random.Generator, q: np.ndarray, subst: np.
     ev = rng.random(L) < r_indel
     kind_del = rng.random(L) < 0.5
     glen = rng.geometric(1.0 / 3.0, size=L)
+    # residues of every potential insertion, drawn at once (inverse CDF of q)
+    ins_len = np.where(ev & ~kind_del, glen, 0)
+    ins_end = np.cumsum(ins_len)
+    qc = np.cumsum(q)
+    qc /= qc[-1]
+    pool = np.minimum(np.searchsorted(qc, rng.random(int(ins_end[-1]) if L else 0), side="right"), K - 1)
     out: List[np.ndarray] = []
     i = 0
     for e in np.flatnonzero(ev):
@@ -132,7 +138,7 @@ def evolve(root: np.ndarray, rng: np.random.Generator, q: np.ndarray, subst: np.
         if kind_del[e]:
             i = e + 1 + int(glen[e])
         else:
-            out.append(rng.choice(K, size=int(glen[e]), p=q))
+            out.append(pool[ins_end[e] - ins_len[e]: ins_end[e]])
             i = e + 1
     if i < L:
         out.append(site[i:])

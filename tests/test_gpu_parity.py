@@ -164,6 +164,22 @@ def test_other_models(B, params):
             k += 1
 
 
+@pytest.mark.parametrize("w", [0.0, 1.0])
+def test_single_model_weight(B, params, w):
+    """w = 1 keeps only the pair-HMM posterior, w = 0 only the partition
+    function's; the other model's backward pass then carries zeros."""
+    fam = W.c1_family()[:4]
+    pw = params.copy(w_hmm=w)
+    _say("single model, w =", w)
+    res = B.qp_posteriors(fam, B.make_params(pw, 0), 0.01)
+    k = 0
+    for i in range(4):
+        for j in range(i + 1, 4):
+            orc = oracle.pair(fam[i], fam[j], pw, per_model=False)
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            k += 1
+
+
 def test_c2_full_size_sampled(B, params):
     """The benchmark workload (200 sequences, 19,900 pairs, one launch);
     the seeded 200-pair sample is checked against the oracle."""
@@ -180,6 +196,66 @@ def test_c2_full_size_sampled(B, params):
     # properties that hold for every pair
     assert np.all(res["val"] >= 0.01) and np.all(res["val"] <= 1.0 + 1e-5)
     assert np.all((res["dist"] >= -1e-6) & (res["dist"] <= 1.0 + 1e-6))
+
+
+def _hip():
+    """The HIP runtime libqp.so is linked against (device buffers for the
+    plan API without a second runtime in the process)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    return hip
+
+
+def _to_device(hip, arr):
+    import ctypes
+    arr = np.ascontiguousarray(arr)
+    p = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(p), max(arr.nbytes, 1)) == 0
+    assert hip.hipMemcpy(p, arr.ctypes.data, arr.nbytes, 1) == 0  # host to device
+    return p
+
+
+def test_device_inputs_unaligned_and_invalid(B, params):
+    """Plan API on device inputs: sequences at odd byte offsets inside a
+    larger buffer give the same result as the host path; a code >= 20 in
+    device memory is reported as QP_EINVAL by the sync, and the plan runs
+    correctly again afterwards."""
+    fam = W.c1_family()[:5]
+    lens = np.array([len(s) for s in fam], dtype=np.int32)
+    ref = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+    _say("device inputs at odd offsets")
+    gap = 3
+    buf = np.full(int(lens.sum()) + gap * (len(fam) + 1), 7, dtype=np.uint8)
+    off = np.zeros(len(fam), dtype=np.int64)
+    pos = gap
+    for k, s in enumerate(fam):
+        off[k] = pos
+        buf[pos:pos + len(s)] = s
+        pos += len(s) + gap
+    bad = buf.copy()
+    bad[off[2] + 5] = 25
+    hip = _hip()
+    d_seqs, d_off, d_bad = _to_device(hip, buf), _to_device(hip, off), _to_device(hip, bad)
+    plan = B.Plan(lens, B.make_params(params, 0), 0.01)
+    try:
+        plan.run(d_seqs.value, d_off.value, 0)
+        plan.sync()
+        res = plan.download()
+        for key in ("row_ptr", "col", "val", "dist", "log_z"):
+            assert np.array_equal(res[key], ref[key]), key
+        plan.run(d_bad.value, d_off.value, 0)
+        assert plan.sync_status() == B.QP_EINVAL
+        plan.run(d_seqs.value, d_off.value, 0)
+        assert plan.sync_status() == B.QP_OK
+        res2 = plan.download()
+        assert np.array_equal(res2["val"], ref["val"])
+    finally:
+        plan.close()
+        for p in (d_seqs, d_off, d_bad):
+            hip.hipFree(p)
 
 
 def test_deterministic(B, params):
