@@ -63,7 +63,12 @@ typedef enum {
     QP_ENOSPC = -7       /* output capacity exceeded (device-resident calls)  */
 } qp_status;
 
-enum { QP_ALPHA = 20, QP_MAX_GAP_CLASSES = 2 };
+/* QP_MAX_SEQ_LEN: longest sequence accepted.  Longer sequences are refused
+ * with QP_EINVAL: banded pairs with more than three 512-row bands are
+ * disabled while a GPU memory fault seen on a 3000-5000 residue workload is
+ * unexplained (a CPU emulation of the same launches found no out-of-bounds
+ * access). */
+enum { QP_ALPHA = 20, QP_MAX_GAP_CLASSES = 2, QP_MAX_SEQ_LEN = 1536 };
 
 /* arithmetic of the dynamic programmes */
 enum {
@@ -185,10 +190,10 @@ typedef struct {
  * Create a plan on the current device.
  *   lens[n]          host copy of the sequence lengths
  *   pair_i, pair_j   NULL for all pairs, else a host pair list of n_pairs
- *   nnz_capacity     initial capacity of the sparse output (entries); 0 lets
- *                    the library estimate it; a run that overflows reports
- *                    QP_ENOSPC from qp_plan_sync and grows the plan so that
- *                    the next run fits
+ *   nnz_capacity     capacity of the sparse output (entries); 0 lets the
+ *                    library estimate it; a run that overflows reports
+ *                    QP_ENOSPC from qp_plan_sync with the entries it needed,
+ *                    and a new plan with at least that capacity must be made
  * Allocates device memory (QP_ENOMEM if it cannot).
  */
 qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
@@ -202,8 +207,9 @@ qp_status qp_plan_create(const int32_t* lens, int32_t n, const int32_t* pair_i, 
 qp_status qp_plan_run(qp_plan* plan, const uint8_t* d_seqs, const int64_t* d_seq_off, void* stream);
 
 /* Wait for the last run on its stream, check for output overflow and fill
- * *res (may be NULL).  QP_ENOSPC if the sparse output did not fit (the plan
- * is grown; run again). */
+ * *res (may be NULL).  QP_ENOSPC if the sparse output did not fit: res->nnz
+ * then holds the number of entries the run produced (every other field is
+ * zero) and the plan is unchanged; create a plan with nnz_capacity >= that. */
 qp_status qp_plan_sync(qp_plan* plan, qp_device_result* res);
 
 /* Copy the last run's outputs to a library-owned host result. */

@@ -260,8 +260,12 @@ class Plan:
         return r
 
     def sync_status(self) -> int:
+        """Status of the last run; on QP_ENOSPC, ``needed_nnz`` holds the
+        entries it produced (a new plan needs at least that capacity)."""
         r = qp_device_result()
-        return int(lib.qp_plan_sync(self.handle, ctypes.byref(r)))
+        st = int(lib.qp_plan_sync(self.handle, ctypes.byref(r)))
+        self.needed_nnz = int(r.nnz) if st == QP_ENOSPC else 0
+        return st
 
     def download(self) -> Dict[str, np.ndarray]:
         out = _P(qp_result)()

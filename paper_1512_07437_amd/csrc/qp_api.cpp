@@ -214,6 +214,12 @@ qp_status validate_lens(const int32_t* lens, int32_t n) {
     if (n > 0 && !lens) return fail(QP_EINVAL, "lens is NULL");
     for (int32_t i = 0; i < n; ++i)
         if (lens[i] < 1) return fail(QP_EINVAL, "lens[%d] = %d < 1 (empty sequences are not allowed)", i, lens[i]);
+    for (int32_t i = 0; i < n; ++i)
+        if (lens[i] > qp::kMaxSeqLen)
+            return fail(QP_EINVAL,
+                        "lens[%d] = %d > %d: sequences needing more than three row bands are disabled pending "
+                        "the cause of a GPU fault on 3000-5000 residue pairs",
+                        i, lens[i], qp::kMaxSeqLen);
     return QP_OK;
 }
 
@@ -635,6 +641,9 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     return QP_OK;
 }
 
+// sparse entries produced by the plan's last synchronised run
+int64_t qp::plan_last_nnz(const qp_plan* pl) { return pl ? pl->last_nnz : 0; }
+
 // device bytes a shaped plan will hold
 int64_t qp::plan_bytes(qp_plan* pl) {
     int64_t b = 0;
@@ -769,37 +778,14 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
     if (flags & 2)
         return fail(QP_EDEVICE, "a row held more entries above the threshold than its staging capacity");
     if ((flags & 1) || nnz > pl->pool_cap) {
-        // grow the sparse output so that the next run fits
-        const int64_t need = nnz + nnz / 16 + 1024;
-        void* p[4] = {};
-        for (int q = 0; q < 4; ++q) {
-            hipError_t e = hipMalloc(&p[q], (size_t)need * 4);
-            if (e != hipSuccess) {
-                for (int r = 0; r < q; ++r) hipFree(p[r]);
-                (void)hipGetLastError();
-                return fail(QP_ENOMEM, "cannot grow the sparse output to %lld entries", (long long)need);
-            }
+        // the plan is left as it is: a caller makes a new plan with at least
+        // this capacity (no buffer is replaced under captured graphs)
+        if (res) {
+            std::memset(res, 0, sizeof(*res));
+            res->nnz = nnz;
         }
-        void* old[4] = {pl->d_pool_col, pl->d_pool_val, pl->d_col, pl->d_val};
-        for (int q = 0; q < 4; ++q) {
-            auto it = std::find(pl->allocs.begin(), pl->allocs.end(), old[q]);
-            if (it != pl->allocs.end()) {
-                hipFree(*it);
-                *it = p[q];
-            }
-        }
-        pl->device_bytes += 4 * 4 * (need - pl->pool_cap);
-        pl->d_pool_col = (int32_t*)p[0];
-        pl->d_pool_val = (float*)p[1];
-        pl->d_col = (int32_t*)p[2];
-        pl->d_val = (float*)p[3];
-        pl->pool_cap = need;
-        pl->args.pool_col = pl->d_pool_col;
-        pl->args.pool_val = pl->d_pool_val;
-        pl->args.pool_cap = need;
-        set_class_args(pl);
-        pl->cap_seqs = nullptr;  // recapture with the new buffers
-        return fail(QP_ENOSPC, "sparse output needed %lld entries; capacity grown, run again", (long long)nnz);
+        return fail(QP_ENOSPC, "sparse output needed %lld entries, capacity %lld; create a plan with "
+                    "nnz_capacity >= %lld", (long long)nnz, (long long)pl->pool_cap, (long long)nnz);
     }
     if (res) {
         res->n_pairs = pl->P;

@@ -16,6 +16,7 @@ constexpr int kTabW = 32;           // stride of a table row (20 y codes, padded
 constexpr int kPadCode = 20;        // x code of rows past the end of a strip
 constexpr int kTabRows = 21;        // 20 residues + the padding row
 constexpr int kRMax = 8;            // largest rows-per-lane instantiation
+constexpr int kMaxSeqLen = 1536;    // longest accepted sequence (QP_MAX_SEQ_LEN)
 constexpr int kRescaleEvery = 8;    // steps between power-of-two rescales
 constexpr int kKeyBins = 1024;      // queue keys: kernel class x cost bin
 constexpr int kCostBins = 64;       // half-octave bins of m*n per kernel class
@@ -118,6 +119,8 @@ qp_status plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, cons
                      const qp_params* params, float thresh, int64_t nnz_capacity, int64_t wave_budget,
                      qp_plan** plan);
 int64_t plan_bytes(qp_plan* pl);
+// sparse entries produced by the plan's last synchronised run
+int64_t plan_last_nnz(const qp_plan* pl);
 qp_status plan_materialize(qp_plan* pl);
 qp_status set_error(qp_status st, const char* msg);
 

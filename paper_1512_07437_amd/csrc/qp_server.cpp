@@ -49,6 +49,7 @@ struct Request {
     hipEvent_t done_ev = nullptr;
     qp_result* result = nullptr;
     qp_status status = QP_OK;
+    bool retried = false;  // one re-run with a plan sized to the output
     std::string error;
     St state = St::Queued;
 };
@@ -111,13 +112,21 @@ qp_status launch(qp_server* s, Request* r) {
     return QP_OK;
 }
 
-// a family's device work has finished: download (or re-run once if the
-// sparse output outgrew its estimate)
+// a family's device work has finished: download (or, once, run again with a
+// fresh plan sized to what the run produced if the sparse output outgrew its
+// estimate; the inputs stay on the device)
 bool complete(qp_server* s, Request* r) {
     qp_status st = qp_plan_download(r->plan, &r->result);
-    if (st == QP_ENOSPC) {
-        // the plan grew its output; run again on the same stream
-        st = qp_plan_run(r->plan, r->d_codes, r->d_off, r->stream);
+    if (st == QP_ENOSPC && !r->retried) {
+        r->retried = true;
+        const int64_t need = qp::plan_last_nnz(r->plan) + 1024;
+        qp_plan_destroy(r->plan);
+        r->plan = nullptr;
+        st = qp::plan_shape(r->lens.data(), (int32_t)r->lens.size(), nullptr, nullptr, 0, &r->params, r->thresh, need,
+                            s->wave_budget, &r->plan);
+        if (st == QP_OK) st = qp::plan_materialize(r->plan);
+        if (st == QP_OK) qp_plan_set_graph(r->plan, 0);
+        if (st == QP_OK) st = qp_plan_run(r->plan, r->d_codes, r->d_off, r->stream);
         if (st == QP_OK && hipEventRecord(r->done_ev, r->stream) == hipSuccess) {
             std::lock_guard<std::mutex> g(s->mu);
             const int64_t nb = qp_plan_device_bytes(r->plan) + (int64_t)r->codes.size() + 8 * (int64_t)r->off.size();

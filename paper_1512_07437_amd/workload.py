@@ -233,14 +233,14 @@ def c4_stream(n_families: int = 2000, seed: int = 4):
         yield t, fam
 
 
-def c5_pairs(n_pairs: int = 64, seed: int = 5) -> List[Tuple[np.ndarray, np.ndarray]]:
+def c5_pairs(n_pairs: int = 64, seed: int = 5, lo: int = 3000, hi: int = 5000) -> List[Tuple[np.ndarray, np.ndarray]]:
     """64 independent divergent pairs, each from its own root, lengths
-    U{3000..5000}, substitution 0.6, indel 0.1."""
+    U{lo..hi} (default 3000..5000), substitution 0.6, indel 0.1."""
     ss = np.random.SeedSequence(seed)
     out = []
     for child in ss.spawn(n_pairs):
         rng = np.random.default_rng(child)
-        lens = rng.integers(3000, 5001, size=2)
+        lens = rng.integers(lo, hi + 1, size=2)
         a, b = make_family(2, lens, child, r_sub=0.6, r_indel=0.1)
         out.append((a, b))
     return out

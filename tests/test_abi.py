@@ -87,6 +87,21 @@ def test_validation_before_device(B, params):
     assert e.value.status == B.QP_EINVAL
 
 
+def test_long_sequences_refused(B, params):
+    """Sequences longer than QP_MAX_SEQ_LEN (1536) are refused before any
+    device call; exactly the limit passes validation (it then needs a GPU)."""
+    p = _good(params)
+    rng = np.random.default_rng(7)
+    long_seq = rng.integers(0, 20, size=1537).astype(np.uint8)
+    short = rng.integers(0, 20, size=50).astype(np.uint8)
+    with pytest.raises(B.QpError) as e:
+        B.qp_posteriors([short, long_seq], p, 0.01)
+    assert e.value.status == B.QP_EINVAL and "1537 > 1536" in str(e.value)
+    with pytest.raises(B.QpError) as e:
+        B.Plan([50, 1537], p, 0.01)
+    assert e.value.status == B.QP_EINVAL
+
+
 def test_empty_family_needs_no_device(B, params):
     p = _good(params)
     for fam in ([], W.c1_family()[:1]):
