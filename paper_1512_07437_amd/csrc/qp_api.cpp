@@ -908,6 +908,8 @@ void qp_plan_destroy(qp_plan* pl) {
     if (!pl) return;
     hipSetDevice(pl->device);
     if (pl->ran && pl->last_g >= 0) hipEventSynchronize(pl->ev[pl->last_g][3]);
+    // nothing of this plan may be in flight when its memory and graphs go
+    if (pl->ran) (void)hipDeviceSynchronize();
     plan_free_device(pl);
     for (int g = 0; g < kNumEventSets; ++g) {
         for (int q = 0; q < 4; ++q)
@@ -1012,17 +1014,9 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
     }
     st = qp_plan_run(pl, d, d_off, s);
     if (st == QP_OK) st = qp_plan_download(pl, out);
-    if (st == QP_ENOSPC) {
-        // the sparse output outgrew the estimate: a fresh plan sized exactly
-        const int64_t need = pl->last_nnz + 1024;
-        trace("host: retry with capacity %lld", (long long)need);
-        hipStreamSynchronize(s);
-        qp_plan_destroy(pl);
-        pl = nullptr;
-        st = qp_plan_create(lens, n, pi, pj, np, params, thresh, need, &pl);
-        if (st == QP_OK) st = qp_plan_run(pl, d, d_off, s);
-        if (st == QP_OK) st = qp_plan_download(pl, out);
-    }
+    // an overflowing run is reported, not retried: runs that continued after
+    // an overflow (with grown or re-created output buffers) faulted the GPU
+    // and the cause is not yet identified
     std::string keep = g_err;
     cleanup();
     g_err = keep;

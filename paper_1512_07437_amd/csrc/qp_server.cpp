@@ -112,12 +112,16 @@ qp_status launch(qp_server* s, Request* r) {
     return QP_OK;
 }
 
-// a family's device work has finished: download (or, once, run again with a
-// fresh plan sized to what the run produced if the sparse output outgrew its
-// estimate; the inputs stay on the device)
+// Re-running a family whose sparse output outgrew its estimate (with a plan
+// sized to what it produced) is switched off: runs that continued after an
+// overflow faulted the GPU and the cause is not yet identified.  Such a
+// family completes with QP_ENOSPC.
+constexpr bool kRetryOverflow = false;
+
+// a family's device work has finished: download (the re-run branch is off)
 bool complete(qp_server* s, Request* r) {
     qp_status st = qp_plan_download(r->plan, &r->result);
-    if (st == QP_ENOSPC && !r->retried) {
+    if (st == QP_ENOSPC && !r->retried && kRetryOverflow) {
         r->retried = true;
         const int64_t need = qp::plan_last_nnz(r->plan) + 1024;
         qp_plan_destroy(r->plan);
