@@ -1014,9 +1014,18 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
     }
     st = qp_plan_run(pl, d, d_off, s);
     if (st == QP_OK) st = qp_plan_download(pl, out);
-    // an overflowing run is reported, not retried: runs that continued after
-    // an overflow (with grown or re-created output buffers) faulted the GPU
-    // and the cause is not yet identified
+    if (st == QP_ENOSPC) {
+        // the sparse output outgrew the estimate: one more run with a fresh
+        // plan sized to what the first run produced
+        const int64_t need = pl->last_nnz + 1024;
+        trace("host: retry with capacity %lld", (long long)need);
+        hipStreamSynchronize(s);
+        qp_plan_destroy(pl);
+        pl = nullptr;
+        st = qp_plan_create(lens, n, pi, pj, np, params, thresh, need, &pl);
+        if (st == QP_OK) st = qp_plan_run(pl, d, d_off, s);
+        if (st == QP_OK) st = qp_plan_download(pl, out);
+    }
     std::string keep = g_err;
     cleanup();
     g_err = keep;
