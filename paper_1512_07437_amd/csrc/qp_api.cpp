@@ -576,9 +576,12 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     pl->fp64 = params->precision == QP_FP64 ? 1 : 0;
 
     // shape of the work per kernel class: pairs, cells, longest rows / columns
-    int64_t rows = 0, est = 0;
+    // sparse-output estimate: 16 entries per row (8 when that pool would
+    // not fit in an eighth of the free device memory), at most 1/thresh
+    int64_t rows = 0, est = 0, est_lo = 0;
     const double inv = std::floor(1.0 / (double)thresh);
-    const int per_row = (int)std::max(1.0, std::min(8.0, inv));
+    const int per_row = (int)std::max(1.0, std::min(16.0, inv));
+    const int per_row_lo = (int)std::max(1.0, std::min(8.0, inv));
     auto count = [&](int32_t m, int32_t c) {
         qp_plan::ClassPlan& cp = pl->cls[qp::pair_class(m)];
         cp.pairs += 1;
@@ -589,6 +592,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         pl->nmax = std::max(pl->nmax, c);
         rows += m + 1;
         est += (int64_t)m * std::min(per_row, c);
+        est_lo += (int64_t)m * std::min(per_row_lo, c);
     };
     if (all) {
         for (int32_t i = 0; i + 1 < n; ++i)
@@ -597,7 +601,6 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         for (int64_t k = 0; k < P; ++k) count(lens[pair_i[k]], lens[pair_j[k]]);
     }
     pl->total_rows = rows;
-    pl->pool_cap = nnz_capacity > 0 ? nnz_capacity : std::max<int64_t>(est + 1024, 1024);
 
     // persistent grid per class: enough waves to fill every SIMD at the
     // kernel's occupancy, bounded by the class's pair count; all classes
@@ -607,6 +610,9 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         (void)hipGetLastError();
         free_b = (size_t)64 << 30;
     }
+    // the pool and the gathered output hold four 4-byte arrays of this size
+    if (16 * est > (int64_t)(free_b / 8)) est = est_lo;
+    pl->pool_cap = nnz_capacity > 0 ? nnz_capacity : std::max<int64_t>(est + 1024, 1024);
     int64_t want_bytes = 0;
     for (int c = 0; c < qp::kClasses; ++c) {
         qp_plan::ClassPlan& cp = pl->cls[c];
@@ -908,8 +914,9 @@ void qp_plan_destroy(qp_plan* pl) {
     if (!pl) return;
     hipSetDevice(pl->device);
     if (pl->ran && pl->last_g >= 0) hipEventSynchronize(pl->ev[pl->last_g][3]);
-    // nothing of this plan may be in flight when its memory and graphs go
-    if (pl->ran) (void)hipDeviceSynchronize();
+    // nothing of a graph-launched plan may be in flight when its memory and
+    // graphs go (eager runs are covered by the end event above)
+    if (pl->ran && pl->exec[0]) (void)hipDeviceSynchronize();
     plan_free_device(pl);
     for (int g = 0; g < kNumEventSets; ++g) {
         for (int q = 0; q < 4; ++q)
