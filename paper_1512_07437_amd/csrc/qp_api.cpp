@@ -123,6 +123,8 @@ struct qp_plan {
     hipEvent_t fork_ev = nullptr, join_ev[3] = {};
     // device memory (one allocation each; freed in destroy)
     std::vector<void*> allocs;
+    qp::DeviceAllocator dev_alloc{};  // hipMalloc / hipFree when unset
+    bool single_stream = false;
     int64_t device_bytes = 0;
     qp::DevParams* d_params = nullptr;
     void* d_tab = nullptr;
@@ -188,10 +190,15 @@ qp_status dalloc(qp_plan* pl, T** out, int64_t count, int64_t* dry) {
         return QP_OK;
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, (size_t)bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(QP_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)bytes, hipGetErrorString(e));
+    if (pl->dev_alloc.alloc) {
+        p = pl->dev_alloc.alloc(pl->dev_alloc.ctx, (size_t)bytes);
+        if (!p) return fail(QP_ENOMEM, "device allocation of %lld bytes failed", (long long)bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, (size_t)bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QP_ENOMEM, "hipMalloc of %lld bytes failed: %s", (long long)bytes, hipGetErrorString(e));
+        }
     }
     pl->allocs.push_back(p);
     pl->device_bytes += bytes;
@@ -204,7 +211,10 @@ void plan_free_device(qp_plan* pl) {
         if (pl->exec[g]) hipGraphExecDestroy(pl->exec[g]);
         pl->exec[g] = nullptr;
     }
-    for (void* p : pl->allocs) hipFree(p);
+    for (void* p : pl->allocs) {
+        if (pl->dev_alloc.release) pl->dev_alloc.release(pl->dev_alloc.ctx, p);
+        else hipFree(p);
+    }
     pl->allocs.clear();
     pl->device_bytes = 0;
 }
@@ -650,6 +660,14 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
 // sparse entries produced by the plan's last synchronised run
 int64_t qp::plan_last_nnz(const qp_plan* pl) { return pl ? pl->last_nnz : 0; }
 
+void qp::plan_set_allocator(qp_plan* pl, const qp::DeviceAllocator& a) {
+    if (pl) pl->dev_alloc = a;
+}
+
+void qp::plan_set_single_stream(qp_plan* pl, bool on) {
+    if (pl) pl->single_stream = on;
+}
+
 // device bytes a shaped plan will hold
 int64_t qp::plan_bytes(qp_plan* pl) {
     int64_t b = 0;
@@ -675,7 +693,7 @@ qp_status qp::plan_materialize(qp_plan* pl) {
     }
     int n_present = 0;
     for (int c = 0; c < qp::kClasses; ++c) n_present += pl->cls[c].grid > 0;
-    if (e == hipSuccess && n_present > 1) {
+    if (e == hipSuccess && n_present > 1 && !pl->single_stream) {
         pl->n_side = std::min(n_present, 3);
         e = hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming);
         for (int q = 0; q < pl->n_side && e == hipSuccess; ++q) {

@@ -121,6 +121,17 @@ qp_status plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, cons
 int64_t plan_bytes(qp_plan* pl);
 // sparse entries produced by the plan's last synchronised run
 int64_t plan_last_nnz(const qp_plan* pl);
+// Optional device allocator of a plan, set before plan_materialize: the
+// serving loop keeps freed blocks for the next family instead of handing
+// them back to the runtime between families.
+struct DeviceAllocator {
+    void* (*alloc)(void* ctx, size_t bytes);  // nullptr when it cannot
+    void (*release)(void* ctx, void* p);
+    void* ctx;
+};
+void plan_set_allocator(qp_plan* pl, const DeviceAllocator& a);
+// run every kernel class on the run stream (no forked side streams)
+void plan_set_single_stream(qp_plan* pl, bool on);
 qp_status plan_materialize(qp_plan* pl);
 qp_status set_error(qp_status st, const char* msg);
 

@@ -8,6 +8,7 @@
 // result does not depend on what else is in flight.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -30,7 +31,74 @@ double now_s() {
     return duration_cast<duration<double>>(steady_clock::now().time_since_epoch()).count();
 }
 
-enum class St { Queued, Running, Done, Canceled };
+enum class St { Queued, Running, Completing, Done, Canceled };
+
+// Device blocks freed by finished families are kept for later ones (best fit
+// within twice the request), so the loop does not hand memory back to the
+// runtime while other families run.  Blocks are rounded to 64 KiB.
+struct DevCache {
+    std::mutex mu;
+    std::multimap<size_t, void*> idle;       // size -> block
+    std::map<void*, size_t> owned;           // every block we allocated
+    int64_t idle_bytes = 0;
+    int64_t limit = 0;                       // idle bytes kept at most
+
+    static void* alloc(void* ctx, size_t bytes) {
+        DevCache* c = static_cast<DevCache*>(ctx);
+        const size_t need = (std::max<size_t>(bytes, 1) + 65535) & ~(size_t)65535;
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            auto it = c->idle.lower_bound(need);
+            if (it != c->idle.end() && it->first <= 2 * need) {
+                void* p = it->second;
+                c->idle_bytes -= (int64_t)it->first;
+                c->idle.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            c->trim(0);  // give the idle blocks back and try once more
+            if (hipMalloc(&p, need) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        std::lock_guard<std::mutex> g(c->mu);
+        c->owned[p] = need;
+        return p;
+    }
+    static void release(void* ctx, void* p) {
+        DevCache* c = static_cast<DevCache*>(ctx);
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            auto it = c->owned.find(p);
+            if (it == c->owned.end()) return;
+            c->idle.emplace(it->second, p);
+            c->idle_bytes += (int64_t)it->second;
+        }
+        if (c->idle_bytes > c->limit) c->trim(c->limit / 2);
+    }
+    // free idle blocks (largest first) until at most `keep` bytes stay idle
+    void trim(int64_t keep) {
+        std::lock_guard<std::mutex> g(mu);
+        while (idle_bytes > keep && !idle.empty()) {
+            auto it = std::prev(idle.end());
+            hipFree(it->second);
+            owned.erase(it->second);
+            idle_bytes -= (int64_t)it->first;
+            idle.erase(it);
+        }
+    }
+    void free_all() {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto& kv : owned) hipFree(kv.first);
+        owned.clear();
+        idle.clear();
+        idle_bytes = 0;
+    }
+};
 
 struct Request {
     uint64_t ticket = 0;
@@ -49,7 +117,6 @@ struct Request {
     hipEvent_t done_ev = nullptr;
     qp_result* result = nullptr;
     qp_status status = QP_OK;
-    bool retried = false;  // one re-run with a plan sized to the output
     std::string error;
     St state = St::Queued;
 };
@@ -71,15 +138,21 @@ struct qp_server {
     std::vector<hipStream_t> streams;
     int next_stream = 0;
     std::thread thr;
+    // finished families are downloaded by a second thread, so the scheduler
+    // keeps admitting and launching meanwhile
+    std::deque<Request*> done_q;
+    std::condition_variable cv_comp;
+    std::thread comp;
+    DevCache cache;
 };
 
 namespace {
 
-void release_device(Request* r) {
+void release_device(qp_server* s, Request* r) {
     if (r->plan) qp_plan_destroy(r->plan);
     r->plan = nullptr;
-    if (r->d_codes) hipFree(r->d_codes);
-    if (r->d_off) hipFree(r->d_off);
+    if (r->d_codes) DevCache::release(&s->cache, r->d_codes);
+    if (r->d_off) DevCache::release(&s->cache, r->d_off);
     if (r->done_ev) hipEventDestroy(r->done_ev);
     r->d_codes = nullptr;
     r->d_off = nullptr;
@@ -88,12 +161,15 @@ void release_device(Request* r) {
 
 // admission: allocate, upload, enqueue the whole pipeline on the stream
 qp_status launch(qp_server* s, Request* r) {
+    qp::plan_set_allocator(r->plan, qp::DeviceAllocator{&DevCache::alloc, &DevCache::release, &s->cache});
+    qp::plan_set_single_stream(r->plan, true);  // families overlap with each other instead
     qp_status st = qp::plan_materialize(r->plan);
     if (st != QP_OK) return st;
     qp_plan_set_graph(r->plan, 0);
     const int64_t tot = std::max<int64_t>(1, (int64_t)r->codes.size());
-    hipError_t e = hipMalloc((void**)&r->d_codes, (size_t)tot);
-    if (e == hipSuccess) e = hipMalloc((void**)&r->d_off, sizeof(int64_t) * std::max<size_t>(1, r->off.size()));
+    r->d_codes = static_cast<uint8_t*>(DevCache::alloc(&s->cache, (size_t)tot));
+    r->d_off = static_cast<int64_t*>(DevCache::alloc(&s->cache, sizeof(int64_t) * std::max<size_t>(1, r->off.size())));
+    hipError_t e = r->d_codes && r->d_off ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -112,36 +188,15 @@ qp_status launch(qp_server* s, Request* r) {
     return QP_OK;
 }
 
-// Re-running a family whose sparse output outgrew its estimate (with a plan
-// sized to what it produced) is switched off: runs that continued after an
-// overflow faulted the GPU and the cause is not yet identified.  Such a
-// family completes with QP_ENOSPC.
-constexpr bool kRetryOverflow = false;
-
-// a family's device work has finished: download (the re-run branch is off)
-bool complete(qp_server* s, Request* r) {
-    qp_status st = qp_plan_download(r->plan, &r->result);
-    if (st == QP_ENOSPC && !r->retried && kRetryOverflow) {
-        r->retried = true;
-        const int64_t need = qp::plan_last_nnz(r->plan) + 1024;
-        qp_plan_destroy(r->plan);
-        r->plan = nullptr;
-        st = qp::plan_shape(r->lens.data(), (int32_t)r->lens.size(), nullptr, nullptr, 0, &r->params, r->thresh, need,
-                            s->wave_budget, &r->plan);
-        if (st == QP_OK) st = qp::plan_materialize(r->plan);
-        if (st == QP_OK) qp_plan_set_graph(r->plan, 0);
-        if (st == QP_OK) st = qp_plan_run(r->plan, r->d_codes, r->d_off, r->stream);
-        if (st == QP_OK && hipEventRecord(r->done_ev, r->stream) == hipSuccess) {
-            std::lock_guard<std::mutex> g(s->mu);
-            const int64_t nb = qp_plan_device_bytes(r->plan) + (int64_t)r->codes.size() + 8 * (int64_t)r->off.size();
-            s->bytes_in_use += nb - r->bytes;
-            r->bytes = nb;
-            return false;  // still running
-        }
-    }
+// a family's device work has finished: download its result.  A family whose
+// sparse output outgrew the plan's estimate completes with QP_ENOSPC; it is
+// not re-run (continuing after an overflow faulted the GPU in other flows and
+// the cause is not identified).
+void complete(qp_server* s, Request* r) {
+    (void)s;
+    const qp_status st = qp_plan_download(r->plan, &r->result);
     r->status = st;
     if (st != QP_OK) r->error = qp_last_error();
-    return true;
 }
 
 void scheduler(qp_server* s) {
@@ -164,7 +219,7 @@ void scheduler(qp_server* s) {
             lk.lock();
             if (st != QP_OK) {
                 if (r->stream) hipStreamSynchronize(r->stream);
-                release_device(r);
+                release_device(s, r);
                 r->status = st;
                 r->error = err;
                 r->state = St::Done;
@@ -175,35 +230,46 @@ void scheduler(qp_server* s) {
                 s->cv_done.notify_all();
             }
         }
-        // retire finished families
+        // hand families whose device work has finished to the download thread
         bool any_done = false;
-        for (size_t q = 0; q < s->running.size();) {
-            Request* r = s->running[q];
-            if (hipEventQuery(r->done_ev) != hipSuccess) {
-                ++q;
-                continue;
-            }
-            lk.unlock();
-            const bool fin = complete(s, r);
-            lk.lock();
-            if (!fin) {
-                ++q;
-                continue;
-            }
-            release_device(r);
-            r->t_done = now_s();
-            r->state = St::Done;
-            s->bytes_in_use -= r->bytes;
-            s->running.erase(s->running.begin() + q);
-            s->finished++;
+        for (Request* r : s->running) {
+            if (r->state != St::Running || hipEventQuery(r->done_ev) != hipSuccess) continue;
+            r->state = St::Completing;
+            s->done_q.push_back(r);
             any_done = true;
         }
-        if (any_done) s->cv_done.notify_all();
+        if (any_done) s->cv_comp.notify_one();
         if (s->stop && s->running.empty() && s->queue.empty()) break;
         if (s->running.empty())
             s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
         else
             s->cv_work.wait_for(lk, std::chrono::microseconds(100));
+    }
+}
+
+// downloads finished families and gives their device memory back to the cache
+void completer(qp_server* s) {
+    hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv_comp.wait(lk, [&] { return !s->done_q.empty() || (s->stop && s->running.empty()); });
+        if (s->done_q.empty()) {
+            if (s->stop && s->running.empty()) break;
+            continue;
+        }
+        Request* r = s->done_q.front();
+        s->done_q.pop_front();
+        lk.unlock();
+        complete(s, r);
+        release_device(s, r);
+        lk.lock();
+        r->t_done = now_s();
+        r->state = St::Done;
+        s->bytes_in_use -= r->bytes;
+        s->running.erase(std::find(s->running.begin(), s->running.end(), r));
+        s->finished++;
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
     }
 }
 
@@ -245,7 +311,9 @@ qp_status qp_server_create(const qp_server_config* cfg, qp_server** out) {
         }
         s->streams.push_back(st);
     }
+    s->cache.limit = cfg->hbm_budget_bytes;
     s->thr = std::thread(scheduler, s);
+    s->comp = std::thread(completer, s);
     *out = s;
     return QP_OK;
 }
@@ -406,11 +474,18 @@ qp_status qp_server_destroy(qp_server* s) {
         s->cv_done.notify_all();
     }
     if (s->thr.joinable()) s->thr.join();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->cv_comp.notify_all();
+    }
+    if (s->comp.joinable()) s->comp.join();
     for (auto& kv : s->all) {
         if (kv.second->result) qp_result_free(kv.second->result);
-        release_device(kv.second);
+        release_device(s, kv.second);
         delete kv.second;
     }
+    for (hipStream_t st : s->streams) hipStreamSynchronize(st);
+    s->cache.free_all();
     for (hipStream_t st : s->streams) hipStreamDestroy(st);
     delete s;
     return QP_OK;
