@@ -273,7 +273,7 @@ def serve_stream(args, say):
     stream = list(W.c4_stream(args.families))
     say("generated %d families" % len(stream))
     free, _ = torch.cuda.mem_get_info()
-    srv = B.Server(hbm_budget_bytes=int(free * 0.6), max_slots=args.slots, n_streams=4)
+    srv = B.Server(hbm_budget_bytes=int(free * 0.6), max_slots=args.slots, n_streams=min(args.slots, 16))
     tickets = [None] * len(stream)
     results = [None] * len(stream)
 
@@ -306,6 +306,8 @@ def serve_stream(args, say):
     if failed:
         say("%d families failed: %s" % (len(failed), failed[:3]))
     lat = np.array([r[2]["done_s"] - r[2]["submit_s"] for r in done])
+    qw = np.array([r[2]["admit_s"] - r[2]["submit_s"] for r in done])   # waiting for a slot / memory
+    sv = np.array([r[2]["done_s"] - r[2]["admit_s"] for r in done])     # admitted until downloaded
     cells = sum(r[2]["cells"] for r in done)
     first = min(r[2]["submit_s"] for r in done)
     last = max(r[2]["done_s"] for r in done)
@@ -328,6 +330,8 @@ def serve_stream(args, say):
                    "cells": int(cells), "pairs": int(sum(r[0] for r in done))},
         "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
         "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "queue_ms_p50_p99": [round(float(np.percentile(qw, q)) * 1e3, 2) for q in (50, 99)],
+        "service_ms_p50_p99": [round(float(np.percentile(sv, q)) * 1e3, 2) for q in (50, 99)],
         "offered_gcups": round(cells / (stream[-1][0] + 1e-9) / 1e9, 3),
         "wall_s": round(t_end - t0, 2),
     }

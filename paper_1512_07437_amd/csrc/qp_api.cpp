@@ -121,6 +121,8 @@ struct qp_plan {
     int n_side = 0;
     hipStream_t side[3] = {};
     hipEvent_t fork_ev = nullptr, join_ev[3] = {};
+    // marks the end of result copies enqueued on the run stream
+    hipEvent_t copy_ev = nullptr;
     // device memory (one allocation each; freed in destroy)
     std::vector<void*> allocs;
     qp::DeviceAllocator dev_alloc{};  // hipMalloc / hipFree when unset
@@ -683,6 +685,7 @@ qp_status qp::plan_materialize(qp_plan* pl) {
         return st;
     }
     hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->copy_ev, hipEventDisableTiming);
     if (e == hipSuccess) {
         for (int g = 0; g < kNumEventSets && e == hipSuccess; ++g) {
             for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipEventCreate(&pl->ev[g][q]);
@@ -793,8 +796,12 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
     int64_t nnz = 0;
     int flags = 0;
     if (pl->P > 0) {
-        HIP_TRY(hipMemcpy(&nnz, pl->d_nnz + pl->P, sizeof(int64_t), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(&flags, pl->d_ints + kIntFlags, sizeof(int), hipMemcpyDeviceToHost));
+        // copies ordered behind the run on its own stream, waited for through
+        // an event: neither the null stream nor other streams are involved
+        HIP_TRY(hipMemcpyAsync(&nnz, pl->d_nnz + pl->P, sizeof(int64_t), hipMemcpyDeviceToHost, pl->last_stream));
+        HIP_TRY(hipMemcpyAsync(&flags, pl->d_ints + kIntFlags, sizeof(int), hipMemcpyDeviceToHost, pl->last_stream));
+        HIP_TRY(hipEventRecord(pl->copy_ev, pl->last_stream));
+        HIP_TRY(hipEventSynchronize(pl->copy_ev));
     }
     pl->last_nnz = nnz;
     trace("sync: done nnz=%lld flags=%d", (long long)nnz, flags);
@@ -863,7 +870,7 @@ qp_status qp_plan_download(qp_plan* pl, qp_result** out) {
     }
     hipError_t e = hipSuccess;
     auto cp = [&](void* dst, const void* src, size_t b) {
-        if (e == hipSuccess && b) e = hipMemcpy(dst, src, b, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && b) e = hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, pl->last_stream);
     };
     cp(r->pair_i, d.pair_i, sizeof(int32_t) * P);
     cp(r->pair_j, d.pair_j, sizeof(int32_t) * P);
@@ -874,6 +881,8 @@ qp_status qp_plan_download(qp_plan* pl, qp_result** out) {
     cp(r->val, d.val, sizeof(float) * d.nnz);
     cp(r->dist, d.dist, sizeof(double) * P);
     cp(r->log_z, d.log_z, sizeof(double) * 2 * P);
+    if (e == hipSuccess) e = hipEventRecord(pl->copy_ev, pl->last_stream);
+    if (e == hipSuccess) e = hipEventSynchronize(pl->copy_ev);
     if (e != hipSuccess) {
         qp_result_free(r);
         return fail(QP_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
@@ -949,6 +958,7 @@ void qp_plan_destroy(qp_plan* pl) {
         if (pl->join_ev[q]) hipEventDestroy(pl->join_ev[q]);
     }
     if (pl->fork_ev) hipEventDestroy(pl->fork_ev);
+    if (pl->copy_ev) hipEventDestroy(pl->copy_ev);
     delete pl;
 }
 
