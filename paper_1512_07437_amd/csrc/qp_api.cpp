@@ -325,9 +325,22 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     ALLOC(pl->d_dist, P);
     ALLOC(pl->d_logz, 2 * P);
     ALLOC(pl->d_scan_tmp, qp::scan_tmp_elems(P + 1) + 8);
-    for (int c = 0; c < qp::kClasses; ++c)
-        if (pl->cls[c].grid > 0)
-            ALLOC(pl->cls[c].d_scratch, (int64_t)pl->cls[c].grid * qp::kWavesPerBlock * pl->cls[c].args.slot_bytes);
+    if (pl->single_stream) {
+        // classes run one after another: one scratch area serves them all
+        int64_t most = 0;
+        for (int c = 0; c < qp::kClasses; ++c)
+            if (pl->cls[c].grid > 0)
+                most = std::max(most, (int64_t)pl->cls[c].grid * qp::kWavesPerBlock * pl->cls[c].args.slot_bytes);
+        char* shared = nullptr;
+        ALLOC(shared, most);
+        for (int c = 0; c < qp::kClasses; ++c)
+            if (pl->cls[c].grid > 0) pl->cls[c].d_scratch = shared;
+    } else {
+        for (int c = 0; c < qp::kClasses; ++c)
+            if (pl->cls[c].grid > 0)
+                ALLOC(pl->cls[c].d_scratch,
+                      (int64_t)pl->cls[c].grid * qp::kWavesPerBlock * pl->cls[c].args.slot_bytes);
+    }
 #undef ALLOC
     if (dry) return QP_OK;
     HIP_TRY(hipMemcpy(pl->d_lens, pl->lens.data(), sizeof(int32_t) * pl->n, hipMemcpyHostToDevice));
@@ -646,14 +659,12 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         for (int c = 0; c < qp::kClasses; ++c)
             if (pl->cls[c].grid > 0) pl->cls[c].grid = std::max(1, (int)(pl->cls[c].grid * f));
     }
+    // a wave budget bounds each class kernel on its own (the serving loop runs
+    // a family's classes one after the other on the family's stream)
     if (wave_budget > 0) {
-        int64_t waves = 0;
-        for (int c = 0; c < qp::kClasses; ++c) waves += (int64_t)pl->cls[c].grid * qp::kWavesPerBlock;
-        if (waves > wave_budget) {
-            const double f = (double)wave_budget / (double)waves;
-            for (int c = 0; c < qp::kClasses; ++c)
-                if (pl->cls[c].grid > 0) pl->cls[c].grid = std::max(1, (int)(pl->cls[c].grid * f));
-        }
+        const int64_t max_blocks = std::max<int64_t>(1, wave_budget / qp::kWavesPerBlock);
+        for (int c = 0; c < qp::kClasses; ++c)
+            if (pl->cls[c].grid > max_blocks) pl->cls[c].grid = (int)max_blocks;
     }
     *plan = pl;
     return QP_OK;
