@@ -332,6 +332,10 @@ def serve_stream(args, say):
         "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
         "queue_ms_p50_p99": [round(float(np.percentile(qw, q)) * 1e3, 2) for q in (50, 99)],
         "service_ms_p50_p99": [round(float(np.percentile(sv, q)) * 1e3, 2) for q in (50, 99)],
+        "service_split_ms_p50": {k: round(float(np.percentile(v, 50)) * 1e3, 2) for k, v in (
+            ("launch", np.array([r[2]["launched_s"] - r[2]["admit_s"] for r in done])),
+            ("device", np.array([r[2]["device_s"] - r[2]["launched_s"] for r in done])),
+            ("download", np.array([r[2]["done_s"] - r[2]["device_s"] for r in done])))},
         "offered_gcups": round(cells / (stream[-1][0] + 1e-9) / 1e9, 3),
         "wall_s": round(t_end - t0, 2),
     }

@@ -259,6 +259,9 @@ typedef struct {
     double admit_s;             /* host clock when admitted                 */
     double done_s;              /* host clock when the result was ready     */
     int64_t cells;              /* sum of m*n over the family's pairs       */
+    double launched_s;          /* host clock when its work was enqueued    */
+    double device_s;            /* host clock when its device work was seen
+                                   finished (the download follows)          */
 } qp_request_times;
 
 /* Create a server on the current device (starts one scheduler thread). */

@@ -58,7 +58,7 @@ class qp_server_config(ctypes.Structure):
 
 class qp_request_times(ctypes.Structure):
     _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
-                ("cells", ctypes.c_int64)]
+                ("cells", ctypes.c_int64), ("launched_s", ctypes.c_double), ("device_s", ctypes.c_double)]
 
 
 # every function the header declares: name -> (restype, argtypes)
@@ -343,7 +343,8 @@ class Server:
             res = result_to_dict(out.contents)
         finally:
             lib.qp_result_free(out)
-        return res, dict(submit_s=tm.submit_s, admit_s=tm.admit_s, done_s=tm.done_s, cells=int(tm.cells))
+        return res, dict(submit_s=tm.submit_s, admit_s=tm.admit_s, done_s=tm.done_s, cells=int(tm.cells),
+                         launched_s=tm.launched_s, device_s=tm.device_s)
 
     def cancel(self, ticket: int) -> int:
         return int(lib.qp_server_cancel(self.handle, ctypes.c_uint64(ticket)))

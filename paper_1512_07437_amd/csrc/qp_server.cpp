@@ -110,7 +110,7 @@ struct Request {
     qp_plan* plan = nullptr;      // shaped at submit, materialised at admission
     int64_t bytes = 0;            // device bytes while running
     int64_t cells = 0;
-    double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0, t_launched = 0, t_device = 0;
     uint8_t* d_codes = nullptr;
     int64_t* d_off = nullptr;
     hipStream_t stream = nullptr;
@@ -216,6 +216,7 @@ void scheduler(qp_server* s) {
             lk.unlock();
             const qp_status st = launch(s, r);
             std::string err = st == QP_OK ? "" : qp_last_error();
+            r->t_launched = now_s();
             lk.lock();
             if (st != QP_OK) {
                 if (r->stream) hipStreamSynchronize(r->stream);
@@ -234,6 +235,7 @@ void scheduler(qp_server* s) {
         bool any_done = false;
         for (Request* r : s->running) {
             if (r->state != St::Running || hipEventQuery(r->done_ev) != hipSuccess) continue;
+            r->t_device = now_s();
             r->state = St::Completing;
             s->done_q.push_back(r);
             any_done = true;
@@ -417,6 +419,8 @@ qp_status qp_server_wait(qp_server* s, uint64_t ticket, int32_t timeout_ms, qp_r
         times->admit_s = r->t_admit;
         times->done_s = r->t_done;
         times->cells = r->cells;
+        times->launched_s = r->t_launched;
+        times->device_s = r->t_device;
     }
     qp_status st = r->status;
     if (r->state == St::Canceled) st = QP_ECANCELED;
