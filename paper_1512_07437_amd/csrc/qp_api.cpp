@@ -681,6 +681,98 @@ void qp::plan_set_single_stream(qp_plan* pl, bool on) {
     if (pl) pl->single_stream = on;
 }
 
+// copy the last run's outputs to a library-owned host result
+qp_status qp::plan_download(qp_plan* pl, qp_result** out, qp::Staging* stg) {
+    if (!out) return fail(QP_EINVAL, "out is NULL");
+    *out = nullptr;
+    qp_device_result d;
+    qp_status st = qp_plan_sync(pl, &d);
+    if (st != QP_OK) return st;
+    qp_result* r = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
+    if (!r) return fail(QP_ENOMEM, "out of host memory");
+    const int64_t P = pl->P;
+    r->n_seqs = pl->n;
+    r->n_pairs = P;
+    r->total_rows = pl->total_rows;
+    r->nnz = d.nnz;
+    r->pair_i = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
+    r->pair_j = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
+    r->row_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
+    r->row_ptr = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(pl->total_rows, 1));
+    r->nnz_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
+    r->col = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(d.nnz, 1));
+    r->val = (float*)std::malloc(sizeof(float) * std::max<int64_t>(d.nnz, 1));
+    r->dist = (double*)std::malloc(sizeof(double) * std::max<int64_t>(P, 1));
+    r->log_z = (double*)std::malloc(sizeof(double) * std::max<int64_t>(2 * P, 1));
+    if (!r->pair_i || !r->pair_j || !r->row_off || !r->row_ptr || !r->nnz_off || !r->col || !r->val || !r->dist ||
+        !r->log_z) {
+        qp_result_free(r);
+        return fail(QP_ENOMEM, "out of host memory");
+    }
+    if (P == 0) {
+        r->row_off[0] = 0;
+        r->nnz_off[0] = 0;
+        *out = r;
+        return QP_OK;
+    }
+    hipError_t e = hipSuccess;
+    // staged copies: chunk k goes through half k % 2; a half is emptied
+    // (its copy waited for, then copied out on the host) before it is reused
+    struct Pending {
+        char* dst = nullptr;
+        size_t len = 0;
+    } pend[2];
+    int half_k = 0;
+    auto drain = [&](int k) {
+        if (e != hipSuccess || !pend[k].dst) return;
+        e = hipEventSynchronize(stg->ev[k]);
+        if (e == hipSuccess) std::memcpy(pend[k].dst, stg->buf + (size_t)k * stg->half, pend[k].len);
+        pend[k].dst = nullptr;
+    };
+    auto cp = [&](void* dst, const void* src, size_t b) {
+        if (e != hipSuccess || !b) return;
+        if (!stg) {
+            e = hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, pl->last_stream);
+            return;
+        }
+        for (size_t off = 0; off < b && e == hipSuccess; off += stg->half) {
+            const size_t len = std::min(stg->half, b - off);
+            drain(half_k);
+            if (e != hipSuccess) return;
+            e = hipMemcpyAsync(stg->buf + (size_t)half_k * stg->half, static_cast<const char*>(src) + off, len,
+                               hipMemcpyDeviceToHost, pl->last_stream);
+            if (e == hipSuccess) e = hipEventRecord(stg->ev[half_k], pl->last_stream);
+            pend[half_k].dst = static_cast<char*>(dst) + off;
+            pend[half_k].len = len;
+            half_k ^= 1;
+        }
+    };
+    cp(r->pair_i, d.pair_i, sizeof(int32_t) * P);
+    cp(r->pair_j, d.pair_j, sizeof(int32_t) * P);
+    cp(r->row_off, d.row_off, sizeof(int64_t) * (P + 1));
+    cp(r->row_ptr, d.row_ptr, sizeof(int32_t) * pl->total_rows);
+    cp(r->nnz_off, d.nnz_off, sizeof(int64_t) * (P + 1));
+    cp(r->col, d.col, sizeof(int32_t) * d.nnz);
+    cp(r->val, d.val, sizeof(float) * d.nnz);
+    cp(r->dist, d.dist, sizeof(double) * P);
+    cp(r->log_z, d.log_z, sizeof(double) * 2 * P);
+    if (stg) {
+        drain(half_k);  // the older pending half first
+        drain(half_k ^ 1);
+    } else {
+        if (e == hipSuccess) e = hipEventRecord(pl->copy_ev, pl->last_stream);
+        if (e == hipSuccess) e = hipEventSynchronize(pl->copy_ev);
+    }
+    if (e != hipSuccess) {
+        qp_result_free(r);
+        return fail(QP_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
+    }
+    collect_timing(pl);
+    r->device_ms = pl->n_timed ? pl->sum_pipe_ms / pl->n_timed : 0.0;
+    *out = r;
+    return QP_OK;
+}
+
 // device bytes a shaped plan will hold
 int64_t qp::plan_bytes(qp_plan* pl) {
     int64_t b = 0;
@@ -846,63 +938,8 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
     return QP_OK;
 }
 
-qp_status qp_plan_download(qp_plan* pl, qp_result** out) {
-    if (!out) return fail(QP_EINVAL, "out is NULL");
-    *out = nullptr;
-    qp_device_result d;
-    qp_status st = qp_plan_sync(pl, &d);
-    if (st != QP_OK) return st;
-    qp_result* r = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
-    if (!r) return fail(QP_ENOMEM, "out of host memory");
-    const int64_t P = pl->P;
-    r->n_seqs = pl->n;
-    r->n_pairs = P;
-    r->total_rows = pl->total_rows;
-    r->nnz = d.nnz;
-    r->pair_i = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
-    r->pair_j = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
-    r->row_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
-    r->row_ptr = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(pl->total_rows, 1));
-    r->nnz_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
-    r->col = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(d.nnz, 1));
-    r->val = (float*)std::malloc(sizeof(float) * std::max<int64_t>(d.nnz, 1));
-    r->dist = (double*)std::malloc(sizeof(double) * std::max<int64_t>(P, 1));
-    r->log_z = (double*)std::malloc(sizeof(double) * std::max<int64_t>(2 * P, 1));
-    if (!r->pair_i || !r->pair_j || !r->row_off || !r->row_ptr || !r->nnz_off || !r->col || !r->val || !r->dist ||
-        !r->log_z) {
-        qp_result_free(r);
-        return fail(QP_ENOMEM, "out of host memory");
-    }
-    if (P == 0) {
-        r->row_off[0] = 0;
-        r->nnz_off[0] = 0;
-        *out = r;
-        return QP_OK;
-    }
-    hipError_t e = hipSuccess;
-    auto cp = [&](void* dst, const void* src, size_t b) {
-        if (e == hipSuccess && b) e = hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, pl->last_stream);
-    };
-    cp(r->pair_i, d.pair_i, sizeof(int32_t) * P);
-    cp(r->pair_j, d.pair_j, sizeof(int32_t) * P);
-    cp(r->row_off, d.row_off, sizeof(int64_t) * (P + 1));
-    cp(r->row_ptr, d.row_ptr, sizeof(int32_t) * pl->total_rows);
-    cp(r->nnz_off, d.nnz_off, sizeof(int64_t) * (P + 1));
-    cp(r->col, d.col, sizeof(int32_t) * d.nnz);
-    cp(r->val, d.val, sizeof(float) * d.nnz);
-    cp(r->dist, d.dist, sizeof(double) * P);
-    cp(r->log_z, d.log_z, sizeof(double) * 2 * P);
-    if (e == hipSuccess) e = hipEventRecord(pl->copy_ev, pl->last_stream);
-    if (e == hipSuccess) e = hipEventSynchronize(pl->copy_ev);
-    if (e != hipSuccess) {
-        qp_result_free(r);
-        return fail(QP_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
-    }
-    collect_timing(pl);
-    r->device_ms = pl->n_timed ? pl->sum_pipe_ms / pl->n_timed : 0.0;
-    *out = r;
-    return QP_OK;
-}
+extern "C" qp_status qp_plan_download(qp_plan* pl, qp_result** out) { return qp::plan_download(pl, out, nullptr); }
+
 
 qp_status qp_plan_timing(qp_plan* pl, double* kernel_ms, double* pipeline_ms, int64_t* n_runs, int32_t reset) {
     if (!pl) return fail(QP_EINVAL, "plan is NULL");

@@ -132,6 +132,16 @@ struct DeviceAllocator {
 void plan_set_allocator(qp_plan* pl, const DeviceAllocator& a);
 // run every kernel class on the run stream (no forked side streams)
 void plan_set_single_stream(qp_plan* pl, bool on);
+// Pinned staging for downloads: results are copied in chunks of `half`
+// bytes through the two halves of `buf`, the copy of one half overlapping
+// the host copy out of the other.  Owned by the caller.
+struct Staging {
+    char* buf = nullptr;
+    size_t half = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+// qp_plan_download, optionally through a staging buffer
+qp_status plan_download(qp_plan* pl, qp_result** out, Staging* stg);
 qp_status plan_materialize(qp_plan* pl);
 qp_status set_error(qp_status st, const char* msg);
 

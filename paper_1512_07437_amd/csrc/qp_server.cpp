@@ -142,7 +142,7 @@ struct qp_server {
     // keeps admitting and launching meanwhile
     std::deque<Request*> done_q;
     std::condition_variable cv_comp;
-    std::thread comp;
+    std::vector<std::thread> comp;
     DevCache cache;
 };
 
@@ -192,9 +192,9 @@ qp_status launch(qp_server* s, Request* r) {
 // sparse output outgrew the plan's estimate completes with QP_ENOSPC; it is
 // not re-run (continuing after an overflow faulted the GPU in other flows and
 // the cause is not identified).
-void complete(qp_server* s, Request* r) {
+void complete(qp_server* s, Request* r, qp::Staging* stg) {
     (void)s;
-    const qp_status st = qp_plan_download(r->plan, &r->result);
+    const qp_status st = qp::plan_download(r->plan, &r->result, stg);
     r->status = st;
     if (st != QP_OK) r->error = qp_last_error();
 }
@@ -240,7 +240,7 @@ void scheduler(qp_server* s) {
             s->done_q.push_back(r);
             any_done = true;
         }
-        if (any_done) s->cv_comp.notify_one();
+        if (any_done) s->cv_comp.notify_all();
         if (s->stop && s->running.empty() && s->queue.empty()) break;
         if (s->running.empty())
             s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
@@ -249,9 +249,23 @@ void scheduler(qp_server* s) {
     }
 }
 
-// downloads finished families and gives their device memory back to the cache
+// downloads finished families (through its own pinned staging buffer) and
+// gives their device memory back to the cache; several run side by side
+constexpr int kCompleters = 3;
+constexpr size_t kStageHalf = (size_t)32 << 20;
+
 void completer(qp_server* s) {
     hipSetDevice(s->device);
+    qp::Staging stg;
+    qp::Staging* use = &stg;
+    if (hipHostMalloc((void**)&stg.buf, 2 * kStageHalf, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&stg.ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&stg.ev[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        use = nullptr;  // direct copies
+    } else {
+        stg.half = kStageHalf;
+    }
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         s->cv_comp.wait(lk, [&] { return !s->done_q.empty() || (s->stop && s->running.empty()); });
@@ -262,7 +276,7 @@ void completer(qp_server* s) {
         Request* r = s->done_q.front();
         s->done_q.pop_front();
         lk.unlock();
-        complete(s, r);
+        complete(s, r, use);
         release_device(s, r);
         lk.lock();
         r->t_done = now_s();
@@ -273,6 +287,10 @@ void completer(qp_server* s) {
         s->cv_done.notify_all();
         s->cv_work.notify_all();
     }
+    lk.unlock();
+    if (stg.buf) hipHostFree(stg.buf);
+    for (hipEvent_t e : stg.ev)
+        if (e) hipEventDestroy(e);
 }
 
 }  // namespace
@@ -315,7 +333,7 @@ qp_status qp_server_create(const qp_server_config* cfg, qp_server** out) {
     }
     s->cache.limit = cfg->hbm_budget_bytes;
     s->thr = std::thread(scheduler, s);
-    s->comp = std::thread(completer, s);
+    for (int q = 0; q < kCompleters; ++q) s->comp.emplace_back(completer, s);
     *out = s;
     return QP_OK;
 }
@@ -482,7 +500,8 @@ qp_status qp_server_destroy(qp_server* s) {
         std::lock_guard<std::mutex> g(s->mu);
         s->cv_comp.notify_all();
     }
-    if (s->comp.joinable()) s->comp.join();
+    for (std::thread& t : s->comp)
+        if (t.joinable()) t.join();
     for (auto& kv : s->all) {
         if (kv.second->result) qp_result_free(kv.second->result);
         release_device(s, kv.second);

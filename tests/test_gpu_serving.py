@@ -52,6 +52,26 @@ def test_alone_equals_mix(B, params):
         assert tm["submit_s"] <= tm["admit_s"] <= tm["done_s"]
 
 
+def test_large_family_served_equals_direct(B, params):
+    """A family whose outputs span several staging chunks (C2: ~42M entries,
+    ~170 MB per array) comes back from the server bit for bit as from
+    qp_posteriors."""
+    p = B.make_params(params)
+    fam = W.c2_family()
+    _say("serving: large family direct")
+    direct = B.qp_posteriors(fam, p, 0.01)
+    _say("serving: large family served")
+    srv = B.Server(hbm_budget_bytes=64 << 30, max_slots=2, n_streams=2)
+    try:
+        res, tm = srv.wait(srv.submit(fam, p, 0.01), timeout_ms=120000)
+    finally:
+        srv.close()
+    assert res["nnz"] > 2 * ((32 << 20) // 4)  # more than two 32 MiB chunks per array
+    for key in KEYS:
+        assert np.array_equal(direct[key], res[key]), key
+    assert tm["admit_s"] <= tm["launched_s"] <= tm["device_s"] <= tm["done_s"]
+
+
 def test_budget_admission(B, params):
     p = B.make_params(params)
     fams = _families()[:3]
