@@ -160,20 +160,50 @@ def _seq_array(seqs: Sequence[np.ndarray]):
     return keep, arr, lens
 
 
-def _np(ptr, count, dtype):
+class _Owned:
+    """Holds a library result; frees it once no array viewing it is left."""
+
+    __slots__ = ("ptr",)
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        ptr, self.ptr = self.ptr, None
+        if ptr is not None and lib is not None:
+            try:
+                lib.qp_result_free(ptr)
+            except Exception:  # interpreter shutdown
+                pass
+
+
+def _view(owner: _Owned, ptr, count, dtype):
+    """Zero-copy array over `count` elements at `ptr`, keeping `owner` alive."""
     if count <= 0:
         return np.zeros(0, dtype=dtype)
-    return np.ctypeslib.as_array(ptr, shape=(int(count),)).astype(dtype, copy=True)
+    dt = np.dtype(dtype)
+    buf = (ctypes.c_char * (int(count) * dt.itemsize)).from_address(ctypes.cast(ptr, ctypes.c_void_p).value)
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=dt, count=int(count))
 
 
-def result_to_dict(r: qp_result) -> Dict[str, np.ndarray]:
-    P, rows, nnz = r.n_pairs, r.total_rows, r.nnz
-    return dict(n_seqs=int(r.n_seqs), n_pairs=int(P), nnz=int(nnz), device_ms=float(r.device_ms),
-                pair_i=_np(r.pair_i, P, np.int32), pair_j=_np(r.pair_j, P, np.int32),
-                row_off=_np(r.row_off, P + 1, np.int64), row_ptr=_np(r.row_ptr, rows, np.int32),
-                nnz_off=_np(r.nnz_off, P + 1, np.int64), col=_np(r.col, nnz, np.int32),
-                val=_np(r.val, nnz, np.float32), dist=_np(r.dist, P, np.float64),
-                log_z=_np(r.log_z, 2 * P, np.float64))
+def _take_result(out) -> Dict[str, np.ndarray]:
+    """Result dict whose arrays view the library result `out` (a pointer
+    from qp_posteriors / qp_plan_download / qp_server_wait) without copying
+    it; the result is freed when the last of the arrays is."""
+    owner = _Owned(out)
+    try:
+        r = out.contents
+        P, rows, nnz = r.n_pairs, r.total_rows, r.nnz
+        return dict(n_seqs=int(r.n_seqs), n_pairs=int(P), nnz=int(nnz), device_ms=float(r.device_ms),
+                    pair_i=_view(owner, r.pair_i, P, np.int32), pair_j=_view(owner, r.pair_j, P, np.int32),
+                    row_off=_view(owner, r.row_off, P + 1, np.int64),
+                    row_ptr=_view(owner, r.row_ptr, rows, np.int32),
+                    nnz_off=_view(owner, r.nnz_off, P + 1, np.int64), col=_view(owner, r.col, nnz, np.int32),
+                    val=_view(owner, r.val, nnz, np.float32), dist=_view(owner, r.dist, P, np.float64),
+                    log_z=_view(owner, r.log_z, 2 * P, np.float64))
+    finally:
+        del owner  # the arrays hold it from here on
 
 
 def qp_posteriors(seqs: Sequence[np.ndarray], params: qp_params, thresh: float) -> Dict[str, np.ndarray]:
@@ -183,10 +213,7 @@ def qp_posteriors(seqs: Sequence[np.ndarray], params: qp_params, thresh: float) 
     st = lib.qp_posteriors(arr, lens.ctypes.data_as(_P(ctypes.c_int32)), len(keep), ctypes.byref(params),
                            ctypes.c_float(thresh), ctypes.byref(out))
     _check(st)
-    try:
-        return result_to_dict(out.contents)
-    finally:
-        lib.qp_result_free(out)
+    return _take_result(out)
 
 
 def qp_posteriors_pairs(seqs: Sequence[np.ndarray], pair_i, pair_j, params: qp_params,
@@ -200,10 +227,7 @@ def qp_posteriors_pairs(seqs: Sequence[np.ndarray], pair_i, pair_j, params: qp_p
                                  pi.ctypes.data_as(_P(ctypes.c_int32)), pj.ctypes.data_as(_P(ctypes.c_int32)),
                                  len(pi), ctypes.byref(params), ctypes.c_float(thresh), ctypes.byref(out))
     _check(st)
-    try:
-        return result_to_dict(out.contents)
-    finally:
-        lib.qp_result_free(out)
+    return _take_result(out)
 
 
 def pair_csr(res: Dict[str, np.ndarray], p: int):
@@ -270,10 +294,7 @@ class Plan:
     def download(self) -> Dict[str, np.ndarray]:
         out = _P(qp_result)()
         _check(lib.qp_plan_download(self.handle, ctypes.byref(out)))
-        try:
-            return result_to_dict(out.contents)
-        finally:
-            lib.qp_result_free(out)
+        return _take_result(out)
 
     def timing(self, reset: bool = False):
         k, p, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
@@ -339,10 +360,7 @@ class Server:
         st = lib.qp_server_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_ms), ctypes.byref(out),
                                 ctypes.byref(tm))
         _check(st)
-        try:
-            res = result_to_dict(out.contents)
-        finally:
-            lib.qp_result_free(out)
+        res = _take_result(out)
         return res, dict(submit_s=tm.submit_s, admit_s=tm.admit_s, done_s=tm.done_s, cells=int(tm.cells),
                          launched_s=tm.launched_s, device_s=tm.device_s)
 

@@ -688,33 +688,16 @@ qp_status qp::plan_download(qp_plan* pl, qp_result** out, qp::Staging* stg) {
     qp_device_result d;
     qp_status st = qp_plan_sync(pl, &d);
     if (st != QP_OK) return st;
-    qp_result* r = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
-    if (!r) return fail(QP_ENOMEM, "out of host memory");
     const int64_t P = pl->P;
-    r->n_seqs = pl->n;
-    r->n_pairs = P;
-    r->total_rows = pl->total_rows;
-    r->nnz = d.nnz;
-    r->pair_i = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
-    r->pair_j = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(P, 1));
-    r->row_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
-    r->row_ptr = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(pl->total_rows, 1));
-    r->nnz_off = (int64_t*)std::malloc(sizeof(int64_t) * (P + 1));
-    r->col = (int32_t*)std::malloc(sizeof(int32_t) * std::max<int64_t>(d.nnz, 1));
-    r->val = (float*)std::malloc(sizeof(float) * std::max<int64_t>(d.nnz, 1));
-    r->dist = (double*)std::malloc(sizeof(double) * std::max<int64_t>(P, 1));
-    r->log_z = (double*)std::malloc(sizeof(double) * std::max<int64_t>(2 * P, 1));
-    if (!r->pair_i || !r->pair_j || !r->row_off || !r->row_ptr || !r->nnz_off || !r->col || !r->val || !r->dist ||
-        !r->log_z) {
-        qp_result_free(r);
-        return fail(QP_ENOMEM, "out of host memory");
-    }
+    qp_result* r = qp::result_alloc(pl->n, P, pl->total_rows, d.nnz);
+    if (!r) return fail(QP_ENOMEM, "out of host memory");
     if (P == 0) {
-        r->row_off[0] = 0;
-        r->nnz_off[0] = 0;
         *out = r;
         return QP_OK;
     }
+    // pinned results take the copies directly; pageable ones go through the
+    // staging buffer, if there is one
+    if (qp::result_pinned(r)) stg = nullptr;
     hipError_t e = hipSuccess;
     // staged copies: chunk k goes through half k % 2; a half is emptied
     // (its copy waited for, then copied out on the host) before it is reused
@@ -1010,20 +993,6 @@ void qp_plan_destroy(qp_plan* pl) {
     delete pl;
 }
 
-void qp_result_free(qp_result* r) {
-    if (!r) return;
-    std::free(r->pair_i);
-    std::free(r->pair_j);
-    std::free(r->row_off);
-    std::free(r->row_ptr);
-    std::free(r->nnz_off);
-    std::free(r->col);
-    std::free(r->val);
-    std::free(r->dist);
-    std::free(r->log_z);
-    std::free(r);
-}
-
 }  // extern "C"
 
 // ------------------------------------------------- blocking host calls
@@ -1046,15 +1015,8 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
     if (pi && np < 0) return fail(QP_EINVAL, "n_pairs < 0");
     if (P == 0) {
         // nothing to compute: an empty result, without touching the device
-        qp_result* r = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
+        qp_result* r = qp::result_alloc(n, 0, 0, 0);
         if (!r) return fail(QP_ENOMEM, "out of host memory");
-        r->n_seqs = n;
-        r->row_off = (int64_t*)std::calloc(1, sizeof(int64_t));
-        r->nnz_off = (int64_t*)std::calloc(1, sizeof(int64_t));
-        if (!r->row_off || !r->nnz_off) {
-            qp_result_free(r);
-            return fail(QP_ENOMEM, "out of host memory");
-        }
         *out = r;
         return QP_OK;
     }

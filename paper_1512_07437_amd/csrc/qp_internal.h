@@ -140,8 +140,15 @@ struct Staging {
     size_t half = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
-// qp_plan_download, optionally through a staging buffer
+// qp_plan_download; results in pageable memory go through the staging
+// buffer when one is given
 qp_status plan_download(qp_plan* pl, qp_result** out, Staging* stg);
+// A result with room for the given counts (every array at least one element;
+// row_off[0] = nnz_off[0] = 0), in one host block that is pinned where that
+// pays off; nullptr when out of host memory.  Freed by qp_result_free.
+qp_result* result_alloc(int32_t n_seqs, int64_t P, int64_t rows, int64_t nnz);
+// whether the result's arrays are in pinned memory
+bool result_pinned(const qp_result* r);
 qp_status plan_materialize(qp_plan* pl);
 qp_status set_error(qp_status st, const char* msg);
 

@@ -400,12 +400,7 @@ qp_status qp_server_submit(qp_server* s, const uint8_t* const* seqs, const int32
     s->all[r->ticket] = r;
     if (n < 2) {
         // nothing to compute: an immediately finished, empty result
-        r->result = static_cast<qp_result*>(std::calloc(1, sizeof(qp_result)));
-        if (r->result) {
-            r->result->n_seqs = n;
-            r->result->row_off = (int64_t*)std::calloc(1, sizeof(int64_t));
-            r->result->nnz_off = (int64_t*)std::calloc(1, sizeof(int64_t));
-        }
+        r->result = qp::result_alloc(n, 0, 0, 0);
         r->state = St::Done;
         r->t_admit = r->t_done = now_s();
         s->finished++;
