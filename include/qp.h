@@ -99,7 +99,9 @@ typedef struct {
 } qp_params;
 
 /*
- * Host-resident result (library-owned; release with qp_result_free).
+ * Host-resident result (library-owned; release with qp_result_free, never
+ * with free()).  The struct and its arrays sit in one host block; blocks of
+ * 1 MiB and more are pinned and reused by later results once freed.
  * Pair p covers rows row_off[p] .. row_off[p+1]-1 of row_ptr (m_p + 1 local
  * row pointers starting at 0) and entries nnz_off[p] .. nnz_off[p+1]-1 of
  * col/val.  col is the 0-based residue index in the second sequence.
