@@ -113,6 +113,50 @@ def cpu_baseline(fam, pairs, sample, params, res, n_seq):
     return cells, dt, worst, ea_worst
 
 
+def per_pair_form(B, lens, params, thresh, ii, jj, sample, res, d_seqs, d_off, sp, batched_gcups, peak, say,
+                  reps=2):
+    """The plain per-pair form (one launch of one wavefront per pair, pair
+    order, no graph, no work queue) on the seeded sample of the same family:
+    its pairs run one after another, so its rate on the sample is its rate on
+    the family.  Its outputs are checked bit for bit against the batched
+    run's for the same pairs.  Not part of the timed region."""
+    import torch
+    si, sj = ii[sample].astype(np.int32), jj[sample].astype(np.int32)
+    cells = int(np.sum(lens[si].astype(np.int64) * lens[sj]))
+    plan = B.Plan(lens, params, thresh, si, sj)
+    try:
+        plan.set_per_pair(True)
+        plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)  # first run: warm-up
+        plan.sync()
+        plan.timing(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        kernel_ms, pipe_ms, _ = plan.timing()
+        plan.sync()
+        pp = plan.download()
+    finally:
+        plan.close()
+    same = True
+    for k, p in enumerate(sample):
+        a0, a1 = res["nnz_off"][p], res["nnz_off"][p + 1]
+        b0, b1 = pp["nnz_off"][k], pp["nnz_off"][k + 1]
+        r0, r1 = res["row_off"][p], res["row_off"][p + 1]
+        q0, q1 = pp["row_off"][k], pp["row_off"][k + 1]
+        same = same and res["dist"][p] == pp["dist"][k] and np.array_equal(res["col"][a0:a1], pp["col"][b0:b1]) \
+            and np.array_equal(res["val"][a0:a1], pp["val"][b0:b1]) \
+            and np.array_equal(res["row_ptr"][r0:r1], pp["row_ptr"][q0:q1])
+    g = cells / dt / 1e9
+    say("per-pair form: %d pairs in %.1f ms (%.3f GCUPS)" % (len(sample), dt * 1e3, g))
+    return {"gcups": round(g, 4), "pairs_per_s": round(len(sample) / dt, 1),
+            "ms_per_pair": round(dt * 1e3 / len(sample), 4), "kernel_span_ms": round(kernel_ms, 3),
+            "frac": round(g * FLOP_PER_CELL / 1e3 / peak, 6),
+            "batched_speedup": round(batched_gcups / g, 1), "identical_to_batched": bool(same),
+            "sample": "%d seeded pairs of the same family (%d cells), one launch per pair" % (len(sample), cells)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +167,7 @@ def main():
     ap.add_argument("--thresh", type=float, default=0.01)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-per-pair", action="store_true", help="skip the plain per-pair form's measurement")
     ap.add_argument("--families", type=int, default=200, help="c4: families replayed")
     ap.add_argument("--slots", type=int, default=8, help="c4: families in flight")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -246,6 +291,9 @@ def main():
         "pair_kernels": classes,
         "all_classes_tflops": round(cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12, 3) if kernel_ms > 0 else None,
     }
+    if not args.no_per_pair and args.workload == "c2":  # a uniform sample: its rate is the family's
+        out["per_pair_form"] = per_pair_form(B, lens, params, args.thresh, ii, jj, sample, res, d_seqs, d_off, sp,
+                                             gcups, peak, say)
     if not args.no_cpu and sample is not None:
         c_cells, c_dt, worst, ea_worst = cpu_baseline(fam, pairs, sample, mp, res, len(fam))
         say("cpu baseline: %d pairs in %.1f s" % (len(sample), c_dt))

@@ -237,6 +237,15 @@ qp_status qp_plan_class_timing(qp_plan* plan, int32_t cls, double* kernel_ms, in
  * (default 1). */
 qp_status qp_plan_set_graph(qp_plan* plan, int32_t use_graph);
 
+/* Run the plan in the plain per-pair form (1) or the batched form (0, the
+ * default).  The per-pair form launches the pair kernel once per pair, one
+ * wavefront, in pair order on the run stream, with no graph and no work
+ * queue; it is the baseline the batched form is measured against.  The
+ * setup, scan and gather steps and every output are the same as in the
+ * batched form; qp_plan_class_timing reports nothing for per-pair runs.
+ * QP_ENOMEM if the per-pair class list cannot be allocated. */
+qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
+
 /* Device bytes held by the plan. */
 int64_t qp_plan_device_bytes(const qp_plan* plan);
 

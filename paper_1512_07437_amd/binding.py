@@ -86,6 +86,7 @@ SIGNATURES = {
     "qp_plan_class_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double),
                                             _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_int32)]),
     "qp_plan_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "qp_plan_set_per_pair": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "qp_plan_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
     "qp_plan_destroy": (None, [ctypes.c_void_p]),
     "qp_server_create": (ctypes.c_int, [_P(qp_server_config), _P(ctypes.c_void_p)]),
@@ -310,6 +311,10 @@ class Plan:
 
     def set_graph(self, on: bool):
         _check(lib.qp_plan_set_graph(self.handle, int(on)))
+
+    def set_per_pair(self, on: bool):
+        """Plain per-pair form (one launch per pair) instead of the batched one."""
+        _check(lib.qp_plan_set_per_pair(self.handle, int(on)))
 
     def device_bytes(self) -> int:
         return int(lib.qp_plan_device_bytes(self.handle))

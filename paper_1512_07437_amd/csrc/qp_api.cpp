@@ -104,6 +104,10 @@ struct qp_plan {
     bool all_pairs = true;
     std::vector<int32_t> lens;
     std::vector<int32_t> list_i, list_j;
+    // plain per-pair form: one launch per pair in pair order (no graph);
+    // pair_cls holds each pair's kernel class
+    bool per_pair = false;
+    std::vector<uint8_t> pair_cls;
     qp_params params{};
     float thresh = 0.f;
     int fp64 = 0;
@@ -171,6 +175,7 @@ struct qp_plan {
     // start / end of each class kernel, recorded on the stream it runs on
     hipEvent_t cev[kNumEventSets][qp::kClasses][2] = {};
     bool ev_pending[kNumEventSets] = {};
+    bool ev_cls[kNumEventSets] = {};  // the run on this event set recorded class events
     int run_idx = 0;
     double sum_kernel_ms = 0.0, sum_pipe_ms = 0.0;
     double sum_class_ms[qp::kClasses] = {};
@@ -414,6 +419,18 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
     HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + kIntFill, pl->d_queue, s));
     HIP_TRY(qp::scan_i64(pl->d_rowoff, P + 1, pl->d_scan_tmp, s));
     if (ev) HIP_TRY(record(ev[1], s, capturing));
+    if (pl->per_pair) {
+        for (int64_t p = 0; p < P; ++p) {
+            const int c = pl->pair_cls[p];
+            HIP_TRY(qp::launch_pair_one(c, pl->fp64, p, pl->cls[c].args, s));
+        }
+        if (ev) HIP_TRY(record(ev[2], s, capturing));
+        HIP_TRY(qp::scan_i64(pl->d_nnz, P + 1, pl->d_scan_tmp, s));
+        HIP_TRY(qp::launch_gather(P, pl->d_nnz, pl->d_base, pl->d_pool_col, pl->d_pool_val, pl->d_col,
+                                  pl->d_val, pl->pool_cap, s));
+        if (ev) HIP_TRY(record(ev[3], s, capturing));
+        return QP_OK;
+    }
     // the kernel classes run concurrently on the side streams (fork / join)
     int present[qp::kClasses], np = 0;
     for (int c = qp::kClasses - 1; c >= 0; --c)
@@ -481,11 +498,13 @@ static void collect_timing(qp_plan* pl) {
             pl->sum_kernel_ms += k;
             pl->sum_pipe_ms += p;
             pl->n_timed += 1;
-            for (int c = 0; c < qp::kClasses; ++c) {
+            for (int c = 0; c < qp::kClasses && pl->ev_cls[g]; ++c) {
                 float ck = 0.f;
                 if (pl->cls[c].grid > 0 &&
                     hipEventElapsedTime(&ck, pl->cev[g][c][0], pl->cev[g][c][1]) == hipSuccess)
                     pl->sum_class_ms[c] += ck;
+                else
+                    (void)hipGetLastError();
             }
         } else {
             (void)hipGetLastError();
@@ -835,9 +854,10 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
     pl->in_seqs = d_seqs;
     pl->in_off = d_seq_off;
     pl->last_stream = s;
+    pl->ev_cls[g] = !pl->per_pair;  // per-pair runs record no class events
     pl->ran = true;
     if (pl->P == 0) return QP_OK;
-    if (pl->use_graph && !pl->graph_broken) {
+    if (pl->use_graph && !pl->graph_broken && !pl->per_pair) {
         if (pl->cap_seqs != d_seqs || pl->cap_off != d_seq_off || !pl->exec[0]) {
             trace("run: capturing graphs");
             qp_status st = capture_graphs(pl);
@@ -865,6 +885,26 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
     pl->ev_pending[g] = true;
     pl->last_g = g;
     pl->run_idx++;
+    return QP_OK;
+}
+
+qp_status qp_plan_set_per_pair(qp_plan* pl, int32_t on) {
+    if (!pl) return fail(QP_EINVAL, "plan is NULL");
+    if (on && pl->pair_cls.size() != (size_t)pl->P) {
+        try {
+            pl->pair_cls.resize((size_t)pl->P);
+        } catch (const std::bad_alloc&) {
+            return fail(QP_ENOMEM, "out of host memory");
+        }
+        int64_t p = 0;
+        if (pl->all_pairs) {
+            for (int32_t i = 0; i + 1 < pl->n; ++i)
+                for (int32_t j = i + 1; j < pl->n; ++j) pl->pair_cls[p++] = (uint8_t)qp::pair_class(pl->lens[i]);
+        } else {
+            for (; p < pl->P; ++p) pl->pair_cls[p] = (uint8_t)qp::pair_class(pl->lens[pl->list_i[p]]);
+        }
+    }
+    pl->per_pair = on != 0;
     return QP_OK;
 }
 

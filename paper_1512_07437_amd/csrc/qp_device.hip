@@ -716,6 +716,24 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
     }
 }
 
+// Plain per-pair form: one launch of one wave per pair, no queue.  The host
+// issues one launch per pair on a single stream, so every launch can use
+// scratch slot 0 of its class.
+template <int R, typename T, bool MULTI>
+__global__ __launch_bounds__(kWave) void k_pair_one(PairArgs a, int64_t p) {
+    using V2 = typename Pair2<T>::type;
+    __shared__ V2 tab[kTabRows * kTabW];
+    const V2* gtab = reinterpret_cast<const V2*>(a.tab);
+    for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const DevConsts c = *a.consts;
+    Coef<T> k;
+    k.tau = (T)c.tau; k.eps1 = (T)c.eps1; k.eps2 = (T)c.eps2; k.c1 = (T)c.c1; k.c2 = (T)c.c2;
+    k.u = (T)c.u; k.o = (T)c.o;
+    process_pair<R, T, MULTI>(a, lane, a.scratch, tab, k, p);
+}
+
 // ------------------------------------------------------ tables (a2 step)
 // Builds the (e_hmm, w_pf) table and the scaled constants from the raw
 // parameters in FP64, rounding once to the kernel precision.
@@ -1036,6 +1054,29 @@ hipError_t launch_pairs(int cls, int fp64, int grid, const PairArgs& a, hipStrea
         case 6: return launch_pairs_r<7, false>(fp64, grid, a, s);
         case 7: return launch_pairs_r<8, false>(fp64, grid, a, s);
         default: return launch_pairs_r<8, true>(fp64, grid, a, s);
+    }
+}
+
+template <int R, bool MULTI>
+static hipError_t launch_pair_one_r(int fp64, int64_t p, const PairArgs& a, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL((k_pair_one<R, double, MULTI>), dim3(1), dim3(kWave), 0, s, a, p);
+    else
+        hipLaunchKernelGGL((k_pair_one<R, float, MULTI>), dim3(1), dim3(kWave), 0, s, a, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_one(int cls, int fp64, int64_t p, const PairArgs& a, hipStream_t s) {
+    switch (cls) {
+        case 0: return launch_pair_one_r<1, false>(fp64, p, a, s);
+        case 1: return launch_pair_one_r<2, false>(fp64, p, a, s);
+        case 2: return launch_pair_one_r<3, false>(fp64, p, a, s);
+        case 3: return launch_pair_one_r<4, false>(fp64, p, a, s);
+        case 4: return launch_pair_one_r<5, false>(fp64, p, a, s);
+        case 5: return launch_pair_one_r<6, false>(fp64, p, a, s);
+        case 6: return launch_pair_one_r<7, false>(fp64, p, a, s);
+        case 7: return launch_pair_one_r<8, false>(fp64, p, a, s);
+        default: return launch_pair_one_r<8, true>(fp64, p, a, s);
     }
 }
 

@@ -108,6 +108,8 @@ hipError_t launch_fill_queue(int64_t n_pairs, const int32_t* key, const int* bin
 int64_t scan_tmp_elems(int64_t n);
 hipError_t scan_i64(int64_t* data, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_pairs(int cls, int fp64, int grid, const PairArgs& a, hipStream_t s);
+// the plain per-pair form: pair p alone, one wave, scratch slot 0 of a.scratch
+hipError_t launch_pair_one(int cls, int fp64, int64_t p, const PairArgs& a, hipStream_t s);
 int pairs_blocks_per_cu(int cls, int fp64);
 hipError_t launch_gather(int64_t n_pairs, const int64_t* nnz_off, const int64_t* pair_base, const int32_t* pool_col, const float* pool_val,
                          int32_t* col, float* val, int64_t cap, hipStream_t s);

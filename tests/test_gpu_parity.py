@@ -270,3 +270,47 @@ def test_deterministic(B, params):
 
 def test_c1_all_pairs_fp64(B, params):
     _c1_all_pairs(B, params, 1)
+
+
+PER_PAIR = [
+    ("c1", None),
+    ("bands_and_single_column", [1100, 90, 700, 1, 2]),
+    ("band_edges", [511, 512, 513, 40]),
+]
+
+
+@pytest.mark.parametrize("name,lens", PER_PAIR, ids=[e[0] for e in PER_PAIR])
+def test_per_pair_form(B, params, name, lens):
+    """The plain per-pair form (one launch of one wave per pair, pair order,
+    no graph) gives the batched form's outputs bit for bit, and both meet the
+    oracle bar."""
+    fam = W.c1_family() if lens is None else W.make_family(len(lens), lens, 7, r_sub=0.3, r_indel=0.05)
+    p = B.make_params(params, 0)
+    lens = np.array([len(x) for x in fam], dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    hip = _hip()
+    d_seqs, d_off = _to_device(hip, np.concatenate(fam).astype(np.uint8)), _to_device(hip, off)
+    out = {}
+    try:
+        for per_pair in (False, True):
+            _say("per-pair form", name, "per_pair=%d" % per_pair)
+            plan = B.Plan(lens, p, 0.01)
+            try:
+                plan.set_per_pair(per_pair)
+                plan.run(d_seqs.value, d_off.value, 0)
+                plan.sync()
+                out[per_pair] = plan.download()
+            finally:
+                plan.close()
+    finally:
+        for q in (d_seqs, d_off):
+            hip.hipFree(q)
+    for key in ("row_off", "row_ptr", "nnz_off", "col", "val", "dist", "log_z"):
+        assert np.array_equal(out[False][key], out[True][key]), key
+    res = out[True]
+    k = 0
+    for i in range(len(fam)):
+        for j in range(i + 1, len(fam)):
+            orc = oracle.pair(fam[i], fam[j], params, per_model=False)
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            k += 1
