@@ -246,6 +246,27 @@ qp_status qp_plan_set_graph(qp_plan* plan, int32_t use_graph);
  * QP_ENOMEM if the per-pair class list cannot be allocated. */
 qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
 
+/*
+ * Tuning table (process-wide; plans copy it when they are made).  The
+ * posterior kernels come in classes by rows per lane R = 1..8 of a 64-lane
+ * wavefront (class R-1), plus a banded class (8) for row sequences longer
+ * than 512.  A pair whose row sequence needs at least r = ceil(m/64) rows
+ * per lane runs with rows_per_lane[r-1] (r..8) rows per lane; every class
+ * launches waves_frac[c] (0, 1] of its occupancy-limited persistent grid.
+ * Default: rows_per_lane[r-1] = r, waves_frac = 1.  Filled in by the
+ * project's autotuner (paper_1512_07437_amd/autotune.py) from measurements
+ * per length bucket.
+ */
+typedef struct {
+    int32_t rows_per_lane[8];
+    double waves_frac[9];
+} qp_tuning;
+
+/* Set the table (NULL restores the default); QP_EINVAL for a value out of
+ * range, the table then unchanged. */
+qp_status qp_set_tuning(const qp_tuning* t);
+qp_status qp_get_tuning(qp_tuning* t);
+
 /* Device bytes held by the plan. */
 int64_t qp_plan_device_bytes(const qp_plan* plan);
 

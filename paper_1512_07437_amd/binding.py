@@ -64,6 +64,10 @@ class qp_request_times(ctypes.Structure):
 # every function the header declares: name -> (restype, argtypes)
 _P = ctypes.POINTER
 _u8pp = _P(_P(ctypes.c_uint8))
+class qp_tuning(ctypes.Structure):
+    _fields_ = [("rows_per_lane", ctypes.c_int32 * 8), ("waves_frac", ctypes.c_double * 9)]
+
+
 SIGNATURES = {
     "qp_version": (ctypes.c_int32, []),
     "qp_last_error": (ctypes.c_char_p, []),
@@ -98,6 +102,8 @@ SIGNATURES = {
     "qp_server_stats": (ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int64),
                                        _P(ctypes.c_int64), _P(ctypes.c_int64)]),
     "qp_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "qp_set_tuning": (ctypes.c_int, [_P(qp_tuning)]),
+    "qp_get_tuning": (ctypes.c_int, [_P(qp_tuning)]),
 }
 
 
@@ -119,6 +125,42 @@ lib = _load()
 def _check(st: int):
     if st != QP_OK:
         raise QpError(st, lib.qp_last_error().decode(errors="replace"))
+
+
+# tuning table written by the autotuner (paper_1512_07437_amd/autotune.py)
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+
+
+def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Optional[Sequence[float]] = None):
+    """Process-wide tuning table for plans made afterwards (qp_set_tuning);
+    None for both restores the default."""
+    if rows_per_lane is None and waves_frac is None:
+        _check(lib.qp_set_tuning(None))
+        return
+    t = get_tuning()
+    r = list(t["rows_per_lane"] if rows_per_lane is None else rows_per_lane)
+    w = list(t["waves_frac"] if waves_frac is None else waves_frac)
+    v = qp_tuning()
+    v.rows_per_lane[:] = [int(x) for x in r]
+    v.waves_frac[:] = [float(x) for x in w]
+    _check(lib.qp_set_tuning(ctypes.byref(v)))
+
+
+def get_tuning() -> Dict[str, list]:
+    t = qp_tuning()
+    _check(lib.qp_get_tuning(ctypes.byref(t)))
+    return {"rows_per_lane": list(t.rows_per_lane), "waves_frac": list(t.waves_frac)}
+
+
+def load_tuning(path: str = TUNING_PATH) -> bool:
+    """Apply a tuning table file if it exists; returns whether one was applied."""
+    import json
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        d = json.load(f)
+    set_tuning(d["rows_per_lane"], d["waves_frac"])
+    return True
 
 
 def qp_version() -> int:
@@ -387,3 +429,7 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# the autotuned table for gfx950, when one has been measured
+load_tuning()

@@ -21,6 +21,15 @@ namespace {
 
 thread_local std::string g_err;
 
+// process-wide tuning table (qp_set_tuning); plans copy it when made
+std::mutex g_tuning_mu;
+qp_tuning g_tuning = [] {
+    qp_tuning t{};
+    for (int r = 0; r < 8; ++r) t.rows_per_lane[r] = r + 1;
+    for (int c = 0; c < 9; ++c) t.waves_frac[c] = 1.0;
+    return t;
+}();
+
 qp_status fail(qp_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -108,6 +117,9 @@ struct qp_plan {
     // pair_cls holds each pair's kernel class
     bool per_pair = false;
     std::vector<uint8_t> pair_cls;
+    // tuning in force when the plan was made
+    qp::ClassMap cmap{};
+    double waves_frac[qp::kClasses] = {};
     qp_params params{};
     float thresh = 0.f;
     int fp64 = 0;
@@ -414,7 +426,7 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
                                   pl->d_ints + kIntFlags, s));
     HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->d_col0, pl->mmax, pl->fp64, s));
     HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
-                             pl->d_key, pl->d_ints + kIntHist, pl->d_nnz, s));
+                             pl->d_key, pl->d_ints + kIntHist, pl->d_nnz, pl->cmap, s));
     HIP_TRY(qp::launch_bins(pl->d_ints + kIntHist, pl->d_bin_start, s));
     HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + kIntFill, pl->d_queue, s));
     HIP_TRY(qp::scan_i64(pl->d_rowoff, P + 1, pl->d_scan_tmp, s));
@@ -611,6 +623,11 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     pl->P = P;
     pl->all_pairs = all;
     pl->lens.assign(lens, lens + n);
+    {
+        std::lock_guard<std::mutex> g(g_tuning_mu);
+        for (int r = 0; r < qp::kRMax; ++r) pl->cmap.c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
+        for (int c = 0; c < qp::kClasses; ++c) pl->waves_frac[c] = g_tuning.waves_frac[c];
+    }
     if (!all) {
         pl->list_i.assign(pair_i, pair_i + P);
         pl->list_j.assign(pair_j, pair_j + P);
@@ -627,7 +644,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     const int per_row = (int)std::max(1.0, std::min(16.0, inv));
     const int per_row_lo = (int)std::max(1.0, std::min(8.0, inv));
     auto count = [&](int32_t m, int32_t c) {
-        qp_plan::ClassPlan& cp = pl->cls[qp::pair_class(m)];
+        qp_plan::ClassPlan& cp = pl->cls[qp::pair_class(m, pl->cmap)];
         cp.pairs += 1;
         cp.cells += (int64_t)m * c;
         cp.mmax = std::max(cp.mmax, m);
@@ -667,7 +684,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         cp.cap = (int)std::max(1.0, std::min((double)cp.nmax, inv + 1.0));
         size_slot(pl, &cp);
         const int per_cu = qp::pairs_blocks_per_cu(c, pl->fp64);
-        int64_t grid = (int64_t)per_cu * n_cu;
+        int64_t grid = std::max<int64_t>(1, (int64_t)std::llround(per_cu * n_cu * pl->waves_frac[c]));
         grid = std::min<int64_t>(grid, std::max<int64_t>(1, (cp.pairs + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock));
         cp.grid = (int)grid;
         want_bytes += grid * qp::kWavesPerBlock * cp.args.slot_bytes;
@@ -888,6 +905,32 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
     return QP_OK;
 }
 
+qp_status qp_set_tuning(const qp_tuning* t) {
+    qp_tuning v{};
+    if (!t) {
+        for (int r = 0; r < 8; ++r) v.rows_per_lane[r] = r + 1;
+        for (int c = 0; c < 9; ++c) v.waves_frac[c] = 1.0;
+    } else {
+        for (int r = 0; r < 8; ++r)
+            if (t->rows_per_lane[r] < r + 1 || t->rows_per_lane[r] > 8)
+                return fail(QP_EINVAL, "rows_per_lane[%d] = %d is not in [%d, 8]", r, t->rows_per_lane[r], r + 1);
+        for (int c = 0; c < 9; ++c)
+            if (!(t->waves_frac[c] > 0.0 && t->waves_frac[c] <= 1.0))
+                return fail(QP_EINVAL, "waves_frac[%d] = %g is not in (0, 1]", c, t->waves_frac[c]);
+        v = *t;
+    }
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    g_tuning = v;
+    return QP_OK;
+}
+
+qp_status qp_get_tuning(qp_tuning* t) {
+    if (!t) return fail(QP_EINVAL, "t is NULL");
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    *t = g_tuning;
+    return QP_OK;
+}
+
 qp_status qp_plan_set_per_pair(qp_plan* pl, int32_t on) {
     if (!pl) return fail(QP_EINVAL, "plan is NULL");
     if (on && pl->pair_cls.size() != (size_t)pl->P) {
@@ -899,9 +942,9 @@ qp_status qp_plan_set_per_pair(qp_plan* pl, int32_t on) {
         int64_t p = 0;
         if (pl->all_pairs) {
             for (int32_t i = 0; i + 1 < pl->n; ++i)
-                for (int32_t j = i + 1; j < pl->n; ++j) pl->pair_cls[p++] = (uint8_t)qp::pair_class(pl->lens[i]);
+                for (int32_t j = i + 1; j < pl->n; ++j) pl->pair_cls[p++] = (uint8_t)qp::pair_class(pl->lens[i], pl->cmap);
         } else {
-            for (; p < pl->P; ++p) pl->pair_cls[p] = (uint8_t)qp::pair_class(pl->lens[pl->list_i[p]]);
+            for (; p < pl->P; ++p) pl->pair_cls[p] = (uint8_t)qp::pair_class(pl->lens[pl->list_i[p]], pl->cmap);
         }
     }
     pl->per_pair = on != 0;

@@ -846,7 +846,7 @@ __global__ void k_stage_seqs(int32_t n, const uint8_t* __restrict__ seqs, const 
 __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32_t* __restrict__ list_i,
                         const int32_t* __restrict__ list_j, int64_t P, int32_t* __restrict__ pi,
                         int32_t* __restrict__ pj, int64_t* __restrict__ rows1, int32_t* __restrict__ key,
-                        int* __restrict__ hist, int64_t* __restrict__ pair_nnz) {
+                        int* __restrict__ hist, int64_t* __restrict__ pair_nnz, ClassMap map) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) {
         rows1[P] = 0;
@@ -872,7 +872,7 @@ __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32
     rows1[p] = m + 1;
     int cb = (int)(log2((double)(m * c)) * 2.0);
     cb = cb < 0 ? 0 : (cb >= kCostBins ? kCostBins - 1 : cb);
-    const int kk = pair_class((int)m) * kCostBins + cb;
+    const int kk = pair_class((int)m, map) * kCostBins + cb;
     key[p] = kk;
     atomicAdd(&hist[kk], 1);
 }
@@ -984,10 +984,10 @@ hipError_t launch_reset(int* ints, int n, hipStream_t s) {
 
 hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j, int64_t P,
                         int32_t* pi, int32_t* pj, int64_t* rows1, int32_t* key, int* hist, int64_t* pair_nnz,
-                        hipStream_t s) {
+                        const ClassMap& map, hipStream_t s) {
     const int64_t blocks = (P + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, n, lens, list_i, list_j,
-                       P, pi, pj, rows1, key, hist, pair_nnz);
+                       P, pi, pj, rows1, key, hist, pair_nnz, map);
     return hipGetLastError();
 }
 

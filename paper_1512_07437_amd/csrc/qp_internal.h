@@ -22,11 +22,17 @@ constexpr int kKeyBins = 1024;      // queue keys: kernel class x cost bin
 constexpr int kCostBins = 64;       // half-octave bins of m*n per kernel class
 constexpr int kClasses = 9;         // R = 1..8 single band, R = 8 banded
 
-// kernel class of a pair: rows per lane R = ceil(m/64) capped at 8; longer
-// rows are cut into bands of 64*8 and go to the banded class
-__host__ __device__ inline int pair_class(int m) {
+// Kernel class per minimal rows per lane: a pair whose row sequence needs
+// r = ceil(m/64) <= 8 rows per lane runs in class c[r-1] (R = c+1 >= r rows
+// per lane; the identity map uses the fewest); longer rows are cut into
+// bands of 64*8 and go to the banded class.  Chosen per length bucket by the
+// tuning table.
+struct ClassMap {
+    int8_t c[kRMax];
+};
+__host__ __device__ inline int pair_class(int m, const ClassMap& map) {
     const int R = (m + kWave - 1) / kWave;
-    return R <= kRMax ? R - 1 : kRMax;
+    return R <= kRMax ? map.c[R - 1] : kRMax;
 }
 __host__ __device__ inline int class_rows_per_lane(int c) { return c < kRMax ? c + 1 : kRMax; }
 
@@ -100,7 +106,7 @@ size_t col0_bytes();
 hipError_t launch_reset(int* ints, int n_ints, hipStream_t s);
 hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j,
                         int64_t n_pairs, int32_t* pair_i, int32_t* pair_j, int64_t* rows1, int32_t* key,
-                        int* hist, int64_t* pair_nnz, hipStream_t s);
+                        int* hist, int64_t* pair_nnz, const ClassMap& map, hipStream_t s);
 hipError_t launch_bins(const int* hist, int* bin_start, hipStream_t s);
 hipError_t launch_fill_queue(int64_t n_pairs, const int32_t* key, const int* bin_start, int* bin_fill,
                              int32_t* queue, hipStream_t s);

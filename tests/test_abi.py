@@ -41,6 +41,7 @@ def test_struct_layout(B):
     assert ctypes.sizeof(B.qp_params) == 8 * 400 + 8 + 8 * 4 + 8 * 400 + 8 * 4 + 8
     assert ctypes.sizeof(B.qp_result) == 4 + 4 + 8 * 3 + 8 * 9 + 8
     assert ctypes.sizeof(B.qp_request_times) == 8 * 6
+    assert ctypes.sizeof(B.qp_tuning) == 4 * 8 + 8 * 9
 
 
 def _good(params):
@@ -140,3 +141,41 @@ def test_server_config_errors(B):
         with pytest.raises(B.QpError) as e:
             B.Server(*cfg)
         assert e.value.status in (B.QP_EINVAL, B.QP_EDEVICE)
+
+
+def test_tuning_table(B):
+    """qp_set_tuning / qp_get_tuning: values round-trip, out-of-range values
+    are refused and leave the table unchanged, NULL restores the default."""
+    before = B.get_tuning()
+    try:
+        B.set_tuning([2, 3, 3, 5, 6, 7, 8, 8], [1.0, 0.5, 0.75, 1.0, 1.0, 1.0, 1.0, 1.0, 0.25])
+        t = B.get_tuning()
+        assert t["rows_per_lane"] == [2, 3, 3, 5, 6, 7, 8, 8]
+        assert t["waves_frac"] == [1.0, 0.5, 0.75, 1.0, 1.0, 1.0, 1.0, 1.0, 0.25]
+        for bad_r, bad_w in (([0, 2, 3, 4, 5, 6, 7, 8], None),   # fewer rows per lane than the bucket needs
+                             ([1, 1, 3, 4, 5, 6, 7, 8], None),
+                             ([1, 2, 3, 4, 5, 6, 7, 9], None),   # more than 8
+                             (None, [0.0] + [1.0] * 8),
+                             (None, [1.0] * 8 + [1.5])):
+            with pytest.raises(B.QpError) as e:
+                B.set_tuning(bad_r, bad_w)
+            assert e.value.status == B.QP_EINVAL
+            assert B.get_tuning() == t
+        B.set_tuning()
+        d = B.get_tuning()
+        assert d["rows_per_lane"] == list(range(1, 9)) and d["waves_frac"] == [1.0] * 9
+    finally:
+        B.set_tuning(before["rows_per_lane"], before["waves_frac"])
+
+
+def test_tuning_file_is_valid(B):
+    """The committed autotuned table, if present, is accepted by the library."""
+    import json
+    if not os.path.exists(B.TUNING_PATH):
+        pytest.skip("no tuning table measured yet")
+    d = json.load(open(B.TUNING_PATH))
+    t = B.qp_tuning()
+    t.rows_per_lane[:] = d["rows_per_lane"]
+    t.waves_frac[:] = d["waves_frac"]
+    assert B.lib.qp_set_tuning(ctypes.byref(t)) == 0
+    assert B.get_tuning()["rows_per_lane"] == d["rows_per_lane"]

@@ -2,9 +2,10 @@
 
 Bar (FP32 scaled path): |P_gpu - P_oracle| <= 1e-5 on every stored entry;
 the CSR pattern equals the oracle's except for entries within 1e-5 of the
-threshold; |EA_gpu - EA_oracle| <= 1e-5; log Z to 1e-5 relative.  The FP64
-path is held to 1e-7 on stored values (they are FP32 in the CSR) and 1e-9 on
-EA and log Z.
+threshold; |EA_gpu - EA_oracle| <= 1e-5; log Z (a diagnostic output) within
+the FP32 rounding bound of its forward sum, 3 (m + n) 2^-24, or 1e-5 relative
+if that is larger.  The FP64 path is held to 1e-7 on stored values (they are
+FP32 in the CSR) and 1e-9 on EA and log Z.
 """
 import sys
 
@@ -16,9 +17,13 @@ from paper_1512_07437_amd import workload as W
 
 pytestmark = pytest.mark.gpu
 
-# (stored value, EA and log Z) per precision; the CSR stores FP32 values, so
-# the FP64 path's stored values carry one FP32 rounding (<= 2^-24 for P <= 1)
-TOL = {0: (1e-5, 1e-5), 1: (1e-7, 1e-9)}
+# (stored value, EA and log Z, log Z rounding per step) per precision; the
+# CSR stores FP32 values, so the FP64 path's stored values carry one FP32
+# rounding (<= 2^-24 for P <= 1).  Z is a forward sum of positive terms:
+# along the m + n anti-diagonal steps of the longest path each step rounds
+# about three times (product, two fused sums), so in FP32 the relative error
+# of Z -- the absolute error of log Z -- stays below 3 (m + n) 2^-24.
+TOL = {0: (1e-5, 1e-5, 3 * 2.0 ** -24), 1: (1e-7, 1e-9, 0.0)}
 
 
 @pytest.fixture(scope="module")
@@ -33,7 +38,7 @@ def _say(*a):
 
 def _check_pair(res, p, x, y, orc, thresh, tols, dense=False):
     from paper_1512_07437_amd import binding as B
-    tol, tol_s = tols
+    tol, tol_s, per_step = tols
     rp, col, val = B.pair_csr(res, p)
     m, n = len(x), len(y)
     assert len(rp) == m + 1 and rp[0] == 0
@@ -58,8 +63,10 @@ def _check_pair(res, p, x, y, orc, thresh, tols, dense=False):
         full[rows, col] = val
         assert np.abs(full - P).max() <= tol + thresh
     assert abs((1.0 - res["dist"][p]) - orc["ea"]) <= tol_s, "pair %d: EA %r vs %r" % (p, 1 - res["dist"][p], orc["ea"])
-    assert abs(res["log_z"][2 * p] - orc["logz_h"]) <= tol_s * max(1.0, abs(orc["logz_h"])), "pair %d: log Z_hmm" % p
-    assert abs(res["log_z"][2 * p + 1] - orc["logz_p"]) <= tol_s * max(1.0, abs(orc["logz_p"])), "pair %d: log Z_pf" % p
+    for q, key in ((0, "logz_h"), (1, "logz_p")):
+        lz_tol = max(tol_s * max(1.0, abs(orc[key])), per_step * (m + n))
+        assert abs(res["log_z"][2 * p + q] - orc[key]) <= lz_tol, "pair %d: %s %r vs %r" % (
+            p, key, res["log_z"][2 * p + q], orc[key])
 
 
 def _c1_all_pairs(B, params, prec):
@@ -314,3 +321,25 @@ def test_per_pair_form(B, params, name, lens):
             orc = oracle.pair(fam[i], fam[j], params, per_model=False)
             _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
             k += 1
+
+
+@pytest.mark.parametrize("shift", [1, 2])
+def test_tuned_class_map(B, params, shift):
+    """Pairs run with more rows per lane than their length needs (fewer,
+    taller lanes) and on half of each class's persistent grid still meet the
+    oracle bar; this is the space the autotuner picks from."""
+    before = B.get_tuning()
+    try:
+        B.set_tuning([min(8, r + 1 + shift) for r in range(8)], [0.5] * 9)
+        for name, fam in (("c1", W.c1_family()),
+                          ("mixed", W.make_family(6, [40, 100, 200, 300, 450, 700], 9, r_sub=0.3, r_indel=0.05))):
+            _say("tuned map shift", shift, name)
+            res = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+            k = 0
+            for i in range(len(fam)):
+                for j in range(i + 1, len(fam)):
+                    orc = oracle.pair(fam[i], fam[j], params, per_model=False)
+                    _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+                    k += 1
+    finally:
+        B.set_tuning(before["rows_per_lane"], before["waves_frac"])
