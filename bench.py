@@ -318,7 +318,11 @@ def serve_stream(args, say):
 
     mp = W.make_params(0)
     params = B.make_params(mp)
-    stream = list(W.c4_stream(args.families))
+    stream = []
+    for t_arr, fam in W.c4_stream(args.families):
+        stream.append((t_arr, fam))
+        if len(stream) % 200 == 0:
+            say("generated %d families" % len(stream))
     say("generated %d families" % len(stream))
     free, _ = torch.cuda.mem_get_info()
     srv = B.Server(hbm_budget_bytes=int(free * 0.6), max_slots=args.slots, n_streams=min(args.slots, 16))
