@@ -34,6 +34,10 @@ METRIC = "all-pairs posterior GCUPS & pairs/s at ≤1e-5 vs FP64 oracle; p99 fam
 # algorithmic FP32 work per DP cell (both models, both passes, posterior,
 # average, MEA, threshold compare)
 FLOP_PER_CELL = 67.0
+# the same work counted as VALU instructions (an FMA is one), against the
+# unpacked issue rate of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_INSTR_PER_CELL = 49.0
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 FP32_VALU_PEAK_TFLOPS = 157.3
 FP64_VALU_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_07437_amd", "csrc", "qp_device.hip")
@@ -288,6 +292,8 @@ def main():
                      "frac": None if achieved is None else round(achieved / peak, 4),
                      "traffic": None if traffic is None else traffic[0] + traffic[1],
                      "traffic_read_write": None if traffic is None else [traffic[0], traffic[1]]},
+        "issue_frac": round(gcups * 1e9 * VALU_INSTR_PER_CELL / VALU_ISSUE_PEAK, 4),
+        "spill_hbm_gbs": None if traffic is None or not dom else round((traffic[0] + traffic[1]) / (dom["avg_ms"] * 1e-3) / 1e9, 1),
         "pair_kernels": classes,
         "all_classes_tflops": round(cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12, 3) if kernel_ms > 0 else None,
     }

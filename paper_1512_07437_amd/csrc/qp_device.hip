@@ -217,7 +217,7 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     V2 sm[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) { sm[r].x = T(0); sm[r].y = T(0); }
-    for (int s = 0; s < S; ++s) {
+    auto fstep = [&](const int s) {
         const int j = s - lane + 1;
         const bool active = used && j >= 1 && j <= n;
         {
@@ -251,33 +251,39 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             rM = qldexp(rM, dH); rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rD = qldexp(rD, dH);
             rgM = qldexp(rgM, dP); rgU = qldexp(rgU, dP); rgD = qldexp(rgD, dP);
         }
+        // match terms of every row first, for all lanes: row r's diagonal
+        // input is row r-1's into-M sum of the previous column (the lane
+        // above's for row 0).  Lanes outside their columns compute values
+        // nobody reads (they go to the spill as stale lines only).  With the
+        // old sums consumed here, the sums of this column overwrite them in
+        // place below.
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const V2 e = tab[xo[r] + ycur];
+            sm[r].x = e.x * (r == 0 ? aD : D[r - 1]);
+            sm[r].y = e.y * (r == 0 ? gaD : gD[r - 1]);
+        }
+        oM = sm[R - 1].x;
+        ogM = sm[R - 1].y;
         if (active) {
-            T upM = rM, upU1 = rU1, upU2 = rU2, dg = aD;
-            T gupM = rgM, gupU = rgU, gdg = gaD;
+            T upM = rM, upU1 = rU1, upU2 = rU2;
+            T gupM = rgM, gupU = rgU;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const V2 e = tab[xo[r] + ycur];
-                const T nM = e.x * dg;
+                const T nM = sm[r].x, ngM = sm[r].y;
                 const T nU1 = fma(k.eps1, upU1, upM);
                 const T nU2 = fma(k.eps2, upU2, upM);
-                const T nD = fma(k.c2, nU2 + W2[r], fma(k.c1, nU1 + W1[r], k.tau * nM));
-                const T ngM = e.y * gdg;
+                D[r] = fma(k.c2, nU2 + W2[r], fma(k.c1, nU1 + W1[r], k.tau * nM));
                 const T ngU = fma(k.u, gupU, gupM);
-                const T ngD = fma(k.o, ngU + gW[r], ngM);
+                gD[r] = fma(k.o, ngU + gW[r], ngM);
                 W1[r] = fma(k.eps1, W1[r], nM);
                 W2[r] = fma(k.eps2, W2[r], nM);
                 gW[r] = fma(k.u, gW[r], ngM);
-                dg = D[r];
-                gdg = gD[r];
-                D[r] = nD;
-                gD[r] = ngD;
                 upM = nM; upU1 = nU1; upU2 = nU2;
                 gupM = ngM; gupU = ngU;
-                sm[r].x = nM;
-                sm[r].y = ngM;
             }
-            oM = upM; oU1 = upU1; oU2 = upU2;
-            ogM = gupM; ogU = gupU;
+            oU1 = upU1; oU2 = upU2;
+            ogU = gupU;
             if (!last && lane == L - 1) {
                 FwdBnd<T> b;
                 b.M = oM; b.U1 = oU1; b.U2 = oU2; b.D = D[R - 1];
@@ -296,7 +302,12 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         if ((s % kRescaleEvery) == 0) (exps + (int64_t)(s / kRescaleEvery) * kWave)[lane] = make_int2(EH, EP);
         aD = rD;
         gaD = rgD;
-        if ((s % kRescaleEvery) == kRescaleEvery - 1) {
+    };
+    // power-of-two rescale closing every block of kRescaleEvery steps (a
+    // separate call after each whole block, so that the step loop carries
+    // one set of registers)
+    auto rescale = [&]() {
+        {
             T mh = T(0), mp = T(0);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -316,7 +327,13 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
             EH -= sh;
             EP -= sp;
         }
+    };
+    int s0 = 0;
+    for (; s0 + kRescaleEvery <= S; s0 += kRescaleEvery) {
+        for (int q = 0; q < kRescaleEvery; ++q) fstep(s0 + q);
+        rescale();
     }
+    for (; s0 < S; ++s0) fstep(s0);
     if (last) {
         // Z = D(m, n): last real row of the band, held by lane L-1
         const int rm = (rows - 1) - (L - 1) * R;
