@@ -83,6 +83,12 @@ def workload(name: str):
         fam = W.c3_family()
         return fam, None, "C3: 1,000 seqs, L log-uniform [50,1500], 499,500 pairs", W.c3_sample(
             [len(s) for s in fam])
+    if name == "c5p":
+        ab = W.c5p_pairs()
+        fam = [s for pair in ab for s in pair]
+        pi = np.arange(0, 2 * len(ab), 2, dtype=np.int32)
+        return fam, (pi, pi + 1), ("C5p: 64 independent pairs, L~U{1000..1536}, substitution 0.3, indel 0.05 "
+                                   "(precision study within the supported lengths)"), np.arange(len(ab))
     if name == "c5":
         raise SystemExit("C5 (lengths 3000..5000) is disabled: sequences longer than 1536 residues are refused "
                          "by the library until a GPU fault seen on that workload is explained")
@@ -224,7 +230,13 @@ def main():
         pl.set_graph(not args.no_graph)
         return pl
 
-    plan = make_plan(0)
+    # c5p: output capacity for the worst case (every row holding floor(1/thresh)+1
+    # entries), so its runs cannot overflow
+    capacity = 0
+    if args.workload == "c5p":
+        per_row = int(np.floor(1.0 / args.thresh)) + 1
+        capacity = int(np.sum(lens[ii].astype(np.int64) * np.minimum(lens[jj], per_row)))
+    plan = make_plan(capacity)
     say("plan: %d pairs, %d cells, %.1f MB device" % (n_pairs, cells, plan.device_bytes() / 1e6))
     sp = stream.cuda_stream
     # the first run checks the estimated sparse-output capacity; if it was too

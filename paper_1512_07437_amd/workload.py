@@ -246,6 +246,21 @@ def c5_pairs(n_pairs: int = 64, seed: int = 5, lo: int = 3000, hi: int = 5000) -
     return out
 
 
+def c5p_pairs(n_pairs: int = 64, seed: int = 55, lo: int = 1000, hi: int = 1536,
+              r_sub: float = 0.3, r_indel: float = 0.05) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """Precision workload within the supported lengths: 64 independent pairs,
+    each from its own root, lengths U{1000..1536} (up to three 512-row
+    bands), with the substitution and indel rates of the other workloads."""
+    ss = np.random.SeedSequence(seed)
+    out = []
+    for child in ss.spawn(n_pairs):
+        rng = np.random.default_rng(child)
+        lens = rng.integers(lo, hi + 1, size=2)
+        a, b = make_family(2, lens, child, r_sub=r_sub, r_indel=r_indel)
+        out.append((a, b))
+    return out
+
+
 def pair_index(i: int, j: int, n: int) -> int:
     """Row-major index of pair (i<j) among the n(n-1)/2 pairs of a family."""
     return i * n - i * (i + 1) // 2 + (j - i - 1)

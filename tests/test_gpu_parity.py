@@ -129,6 +129,21 @@ def test_edge_shapes(B, params, name, lens):
             k += 1
 
 
+@pytest.mark.parametrize("name,lens", [e for e in EDGE if e[0] in ("lane_edges", "band_edges", "two_bands")],
+                         ids=["lane_edges", "band_edges", "two_bands"])
+def test_edge_shapes_fp64(B, params, name, lens):
+    """The FP64 path on every single-band class boundary and on banded rows."""
+    fam = W.make_family(len(lens), lens, 7, r_sub=0.3, r_indel=0.05)
+    _say("edge fp64", name, lens)
+    res = B.qp_posteriors(fam, B.make_params(params, 1), 0.01)
+    k = 0
+    for i in range(len(fam)):
+        for j in range(i + 1, len(fam)):
+            orc = oracle.pair(fam[i], fam[j], params, per_model=False)
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[1])
+            k += 1
+
+
 def test_unrelated_and_identical(B, params):
     rng = np.random.default_rng(11)
     a = rng.integers(0, 20, 150).astype(np.uint8)
