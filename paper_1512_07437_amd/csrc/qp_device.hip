@@ -50,6 +50,27 @@ template <typename T> struct BwdBnd {
     int FH, FP;
 };
 
+// Spill traffic is written once and read back once, long after any cache
+// could keep it: streaming (non-temporal) stores and loads, so it does not
+// displace other lines from L2 and the last-level cache.
+template <typename V2>
+__device__ __forceinline__ void spill_store(V2* p, const V2& v) {
+    using S = decltype(v.x);
+    typedef S N2 __attribute__((ext_vector_type(2)));
+    const N2 n = {v.x, v.y};
+    __builtin_nontemporal_store(n, reinterpret_cast<N2*>(p));
+}
+template <typename V2>
+__device__ __forceinline__ V2 spill_load(const V2* p) {
+    using S = decltype(p->x);
+    typedef S N2 __attribute__((ext_vector_type(2)));
+    const N2 n = __builtin_nontemporal_load(reinterpret_cast<const N2*>(p));
+    V2 v;
+    v.x = n[0];
+    v.y = n[1];
+    return v;
+}
+
 template <typename T> struct Coef {
     T tau, eps1, eps2, c1, c2, u, o;
 };
@@ -295,7 +316,7 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         {
             V2* sp = spill + (int64_t)s * R * kWave;  // uniform step base
 #pragma unroll
-            for (int r = 0; r < R; ++r) sp[r * kWave + lane] = sm[r];
+            for (int r = 0; r < R; ++r) spill_store(&sp[r * kWave + lane], sm[r]);
         }
         // exponents change only at the rescale closing every block of
         // kRescaleEvery steps: one record per block, written by every lane
@@ -411,7 +432,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     if (used && lead == 0) {
         const V2* sp = spill + (int64_t)(S - 1) * R * kWave;
 #pragma unroll
-        for (int r = 0; r < R; ++r) fa[r] = sp[r * kWave + lane];
+        for (int r = 0; r < R; ++r) fa[r] = spill_load(&sp[r * kWave + lane]);
         ea = (exps + (int64_t)((S - 1) / kRescaleEvery) * kWave)[lane];
     }
     BwdBnd<T> bq;  // lane L-1 of an upper band: boundary record of its next column
@@ -435,7 +456,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         {
             const V2* sp = spill + (int64_t)tn * R * kWave;
 #pragma unroll
-            for (int r = 0; r < R; ++r) fn[r] = sp[r * kWave + lane];
+            for (int r = 0; r < R; ++r) fn[r] = spill_load(&sp[r * kWave + lane]);
             en = (exps + (int64_t)(tn / kRescaleEvery) * kWave)[lane];
         }
         // ---- exchange with the lane below
