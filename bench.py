@@ -309,6 +309,13 @@ def main():
         "pair_kernels": classes,
         "all_classes_tflops": round(cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12, 3) if kernel_ms > 0 else None,
     }
+    if pairs is None and len(fam) > 1:
+        # the next stage on the host: guide tree and tree-guided distances
+        t_gt = time.perf_counter()
+        joins, heights = B.guide_tree(res["dist"], len(fam))
+        B.tree_distance(joins, len(fam))
+        out["guide_tree"] = {"ms": round((time.perf_counter() - t_gt) * 1e3, 2), "seqs": len(fam),
+                             "root_height": round(float(heights[-1]), 6), "where": "host, after the timed region"}
     if not args.no_per_pair and args.workload == "c2":  # a uniform sample: its rate is the family's
         out["per_pair_form"] = per_pair_form(B, lens, params, args.thresh, ii, jj, sample, res, d_seqs, d_off, sp,
                                              gcups, peak, say)

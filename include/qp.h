@@ -273,6 +273,38 @@ int64_t qp_plan_device_bytes(const qp_plan* plan);
 void qp_plan_destroy(qp_plan* plan);
 
 /* ------------------------------------------------------------------------
+ * Guide tree (the stage after the posteriors; paper: Methods, opening
+ * paragraph -- weighted UPGMA on the pairwise distances -- and "Selective
+ * consistency" -- the tree-guided distance).  Host memory, host computation.
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Weighted UPGMA (WPGMA) over n sequences.
+ *   dist     [n(n-1)/2] distances in pair order p = i*n - i*(i+1)/2 + (j-i-1)
+ *            (the dist array of qp_result); finite values
+ *   merges   [2(n-1)] out: step k joins clusters merges[2k] < merges[2k+1];
+ *            ids 0..n-1 are the sequences, id n+k is the cluster made at step k
+ *   heights  [n-1] out: half the distance at which step k joins
+ * Each step joins the two closest clusters; the joined cluster's distance to
+ * any other is the plain mean of the two (each side weighs the same,
+ * whatever its size).  Equal distances: the pair with the smaller smaller
+ * id, then the smaller larger id.  QP_EINVAL for n outside [1, 32768], a
+ * NULL array (n > 1) or a value that is not finite; QP_ENOMEM when the
+ * working copy of the distances cannot be allocated.  n = 1: nothing to do.
+ */
+qp_status qp_guide_tree(const double* dist, int32_t n, int32_t* merges, double* heights);
+
+/*
+ * Tree-guided distance of every pair (i < j), in pair order: the number of
+ * nodes (sequences and joins) of the smallest subtree holding both, i.e. of
+ * the subtree under their first common join, 2L - 1 for L sequences under it.
+ *   merges   [2(n-1)] a tree as qp_guide_tree writes it
+ *   out      [n(n-1)/2] out
+ * QP_EINVAL if a step does not join two existing, not yet joined clusters.
+ */
+qp_status qp_tree_distance(const int32_t* merges, int32_t n, int32_t* out);
+
+/* ------------------------------------------------------------------------
  * Serving: families arrive over time; each is admitted when the free device
  * memory budget covers its workspace and outputs and a slot is free; admitted
  * families run concurrently on a pool of streams (continuous batching), and

@@ -103,6 +103,8 @@ SIGNATURES = {
                                        _P(ctypes.c_int64), _P(ctypes.c_int64)]),
     "qp_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "qp_set_tuning": (ctypes.c_int, [_P(qp_tuning)]),
+    "qp_guide_tree": (ctypes.c_int, [_P(ctypes.c_double), ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_double)]),
+    "qp_tree_distance": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32)]),
     "qp_get_tuning": (ctypes.c_int, [_P(qp_tuning)]),
 }
 
@@ -161,6 +163,30 @@ def load_tuning(path: str = TUNING_PATH) -> bool:
         d = json.load(f)
     set_tuning(d["rows_per_lane"], d["waves_frac"])
     return True
+
+
+def guide_tree(dist, n: int):
+    """Weighted UPGMA on the condensed distances (pair order of a result's
+    ``dist``): (joins [n-1, 2] int32, heights [n-1] float64)."""
+    d = np.ascontiguousarray(dist, dtype=np.float64)
+    if d.shape != (n * (n - 1) // 2,):
+        raise ValueError("dist must hold n(n-1)/2 values")
+    joins = np.zeros((max(n - 1, 0), 2), dtype=np.int32)
+    heights = np.zeros(max(n - 1, 0), dtype=np.float64)
+    _check(lib.qp_guide_tree(d.ctypes.data_as(_P(ctypes.c_double)), int(n),
+                             joins.ctypes.data_as(_P(ctypes.c_int32)), heights.ctypes.data_as(_P(ctypes.c_double))))
+    return joins, heights
+
+
+def tree_distance(joins, n: int) -> np.ndarray:
+    """Tree-guided distance of every pair (pair order): nodes of the subtree
+    under their lowest common ancestor."""
+    j = np.ascontiguousarray(joins, dtype=np.int32).reshape(-1)
+    if j.shape != (2 * max(n - 1, 0),):
+        raise ValueError("joins must hold n-1 rows of two ids")
+    out = np.zeros(n * (n - 1) // 2, dtype=np.int32)
+    _check(lib.qp_tree_distance(j.ctypes.data_as(_P(ctypes.c_int32)), int(n), out.ctypes.data_as(_P(ctypes.c_int32))))
+    return out
 
 
 def qp_version() -> int:
