@@ -163,6 +163,28 @@ qp_status qp_posteriors_pairs(const uint8_t* const* seqs, const int32_t* lens, i
 /* Release a result (NULL-safe). */
 void qp_result_free(qp_result* r);
 
+/*
+ * Output size with a guarantee (the sparse output is what limits family size
+ * in memory; paper: "Selective consistency", footnote on the sparsity, and
+ * the closing discussion).  The posteriors of a row sum to at most one, so a
+ * row keeps at most floor(1/thresh) entries at or above the threshold; the
+ * kernels give each row floor(1/thresh) + 1 slots (rounding slack), at most
+ * its pair's column count.
+ *
+ * qp_output_bound: *entries = sum over pairs of m * min(n, floor(1/thresh)+1)
+ * for the family (pair_i = pair_j = NULL: all pairs i < j) or the pair list.
+ *
+ * qp_threshold_for_budget: *thresh = the smallest threshold whose bound is
+ * at most max_entries (when even the dense output fits, the threshold at
+ * which rows first keep every column).  QP_ENOSPC if even thresh = 1 (two
+ * slots per row) does not fit.  Both: QP_EINVAL for invalid lengths, pairs
+ * or threshold.  Host computation only.
+ */
+qp_status qp_output_bound(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                          int64_t n_pairs, float thresh, int64_t* entries);
+qp_status qp_threshold_for_budget(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                                  int64_t n_pairs, int64_t max_entries, float* thresh);
+
 /* ------------------------------------------------------------------------
  * Device-resident form.  A plan fixes the family shape (lengths, pair list,
  * parameters, threshold), owns the device workspace and output buffers and
@@ -193,7 +215,8 @@ typedef struct {
  *   lens[n]          host copy of the sequence lengths
  *   pair_i, pair_j   NULL for all pairs, else a host pair list of n_pairs
  *   nnz_capacity     capacity of the sparse output (entries); 0 lets the
- *                    library estimate it; a run that overflows reports
+ *                    library estimate it; -1 sizes it to qp_output_bound, so
+ *                    no run can overflow; a run that overflows reports
  *                    QP_ENOSPC from qp_plan_sync with the entries it needed,
  *                    and a new plan with at least that capacity must be made
  * Allocates device memory (QP_ENOMEM if it cannot).

@@ -103,6 +103,11 @@ SIGNATURES = {
                                        _P(ctypes.c_int64), _P(ctypes.c_int64)]),
     "qp_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "qp_set_tuning": (ctypes.c_int, [_P(qp_tuning)]),
+    "qp_output_bound": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                       ctypes.c_int64, ctypes.c_float, _P(ctypes.c_int64)]),
+    "qp_threshold_for_budget": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32),
+                                               _P(ctypes.c_int32), ctypes.c_int64, ctypes.c_int64,
+                                               _P(ctypes.c_float)]),
     "qp_guide_tree": (ctypes.c_int, [_P(ctypes.c_double), ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_double)]),
     "qp_tree_distance": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32)]),
     "qp_get_tuning": (ctypes.c_int, [_P(qp_tuning)]),
@@ -163,6 +168,33 @@ def load_tuning(path: str = TUNING_PATH) -> bool:
         d = json.load(f)
     set_tuning(d["rows_per_lane"], d["waves_frac"])
     return True
+
+
+def _pairs_args(lens, pair_i, pair_j):
+    lens = np.ascontiguousarray(lens, dtype=np.int32)
+    if pair_i is None and pair_j is None:
+        return lens, None, None, 0, (lens,)
+    pi = np.ascontiguousarray(pair_i, dtype=np.int32)
+    pj = np.ascontiguousarray(pair_j, dtype=np.int32)
+    return lens, pi.ctypes.data_as(_P(ctypes.c_int32)), pj.ctypes.data_as(_P(ctypes.c_int32)), len(pi), (lens, pi, pj)
+
+
+def output_bound(lens, thresh: float, pair_i=None, pair_j=None) -> int:
+    """Entries the sparse output can reach at this threshold (no run exceeds it)."""
+    lens, pi, pj, np_, keep = _pairs_args(lens, pair_i, pair_j)
+    e = ctypes.c_int64()
+    _check(lib.qp_output_bound(lens.ctypes.data_as(_P(ctypes.c_int32)), len(lens), pi, pj, np_,
+                               ctypes.c_float(thresh), ctypes.byref(e)))
+    return int(e.value)
+
+
+def threshold_for_budget(lens, max_entries: int, pair_i=None, pair_j=None) -> float:
+    """Smallest threshold whose output bound fits max_entries."""
+    lens, pi, pj, np_, keep = _pairs_args(lens, pair_i, pair_j)
+    t = ctypes.c_float()
+    _check(lib.qp_threshold_for_budget(lens.ctypes.data_as(_P(ctypes.c_int32)), len(lens), pi, pj, np_,
+                                       int(max_entries), ctypes.byref(t)))
+    return float(t.value)
 
 
 def guide_tree(dist, n: int):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
@@ -45,6 +46,13 @@ qp_status fail(qp_status st, const char* fmt, ...) {
         hipError_t _e = (expr);                                                                \
         if (_e != hipSuccess) return fail(QP_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
     } while (0)
+
+// Most entries one row of a pair with c columns can keep: the posteriors of
+// a row sum to at most one, so at most floor(1/thresh) of them reach the
+// threshold; one more covers rounding (the kernels' per-row capacity).
+int64_t row_bound(int32_t c, float thresh) {
+    return (int64_t)std::min((double)c, std::floor(1.0 / (double)thresh) + 1.0);
+}
 
 constexpr int kNumEventSets = 8;
 // layout of the plan's int counters
@@ -600,6 +608,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     if (st != QP_OK) return st;
     if ((st = qp_params_check(params)) != QP_OK) return st;
     if (!(thresh > 0.0f && thresh <= 1.0f)) return fail(QP_EINVAL, "thresh = %g is not in (0, 1]", (double)thresh);
+    if (nnz_capacity < -1) return fail(QP_EINVAL, "nnz_capacity = %lld < -1", (long long)nnz_capacity);
     const bool all = pair_i == nullptr && pair_j == nullptr;
     if (!all) {
         if (!pair_i || !pair_j) return fail(QP_EINVAL, "pair_i and pair_j must both be given");
@@ -639,7 +648,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     // shape of the work per kernel class: pairs, cells, longest rows / columns
     // sparse-output estimate: 16 entries per row (8 when that pool would
     // not fit in an eighth of the free device memory), at most 1/thresh
-    int64_t rows = 0, est = 0, est_lo = 0;
+    int64_t rows = 0, est = 0, est_lo = 0, bound = 0;
     const double inv = std::floor(1.0 / (double)thresh);
     const int per_row = (int)std::max(1.0, std::min(16.0, inv));
     const int per_row_lo = (int)std::max(1.0, std::min(8.0, inv));
@@ -654,6 +663,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         rows += m + 1;
         est += (int64_t)m * std::min(per_row, c);
         est_lo += (int64_t)m * std::min(per_row_lo, c);
+        bound += (int64_t)m * row_bound(c, thresh);
     };
     if (all) {
         for (int32_t i = 0; i + 1 < n; ++i)
@@ -673,7 +683,9 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     }
     // the pool and the gathered output hold four 4-byte arrays of this size
     if (16 * est > (int64_t)(free_b / 8)) est = est_lo;
-    pl->pool_cap = nnz_capacity > 0 ? nnz_capacity : std::max<int64_t>(est + 1024, 1024);
+    pl->pool_cap = nnz_capacity > 0    ? nnz_capacity
+                   : nnz_capacity == -1 ? std::max<int64_t>(bound, 1)
+                                        : std::max<int64_t>(est + 1024, 1024);
     int64_t want_bytes = 0;
     for (int c = 0; c < qp::kClasses; ++c) {
         qp_plan::ClassPlan& cp = pl->cls[c];
@@ -905,6 +917,79 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
     return QP_OK;
 }
 
+// (rows, columns) of every pair of a family or pair list, after validation
+static qp_status visit_pairs(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                             int64_t n_pairs, const std::function<void(int32_t, int32_t)>& f) {
+    qp_status st = validate_lens(lens, n);
+    if (st != QP_OK) return st;
+    if (pair_i == nullptr && pair_j == nullptr) {
+        for (int32_t i = 0; i + 1 < n; ++i)
+            for (int32_t j = i + 1; j < n; ++j) f(lens[i], lens[j]);
+        return QP_OK;
+    }
+    if (!pair_i || !pair_j) return fail(QP_EINVAL, "pair_i and pair_j must both be given");
+    if (n_pairs < 0) return fail(QP_EINVAL, "n_pairs < 0");
+    for (int64_t k = 0; k < n_pairs; ++k)
+        if (pair_i[k] < 0 || pair_i[k] >= n || pair_j[k] < 0 || pair_j[k] >= n || pair_i[k] == pair_j[k])
+            return fail(QP_EINVAL, "pair %lld = (%d, %d) is not a pair of two sequences of the family", (long long)k,
+                        pair_i[k], pair_j[k]);
+    for (int64_t k = 0; k < n_pairs; ++k) f(lens[pair_i[k]], lens[pair_j[k]]);
+    return QP_OK;
+}
+
+qp_status qp_output_bound(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                          int64_t n_pairs, float thresh, int64_t* entries) {
+    if (!entries) return fail(QP_EINVAL, "entries is NULL");
+    if (!(thresh > 0.0f && thresh <= 1.0f)) return fail(QP_EINVAL, "thresh = %g is not in (0, 1]", (double)thresh);
+    int64_t total = 0;
+    qp_status st = visit_pairs(lens, n, pair_i, pair_j, n_pairs,
+                               [&](int32_t m, int32_t c) { total += (int64_t)m * row_bound(c, thresh); });
+    if (st != QP_OK) return st;
+    *entries = total;
+    return QP_OK;
+}
+
+qp_status qp_threshold_for_budget(const int32_t* lens, int32_t n, const int32_t* pair_i, const int32_t* pair_j,
+                                  int64_t n_pairs, int64_t max_entries, float* thresh) {
+    if (!thresh) return fail(QP_EINVAL, "thresh is NULL");
+    std::vector<std::pair<int32_t, int32_t>> shapes;
+    int32_t cmax = 1;
+    qp_status st = visit_pairs(lens, n, pair_i, pair_j, n_pairs, [&](int32_t m, int32_t c) {
+        shapes.emplace_back(m, c);
+        cmax = std::max(cmax, c);
+    });
+    if (st != QP_OK) return st;
+    // entries when every row keeps at most K: non-decreasing in K
+    auto at = [&](int64_t K) {
+        int64_t t = 0;
+        for (const auto& sc : shapes) t += (int64_t)sc.first * std::min<int64_t>(sc.second, K);
+        return t;
+    };
+    // thresh = 1 still leaves two per row (one entry, plus the rounding slack)
+    if (at(2) > max_entries)
+        return fail(QP_ENOSPC, "even thresh = 1 may need %lld entries, more than %lld", (long long)at(2),
+                    (long long)max_entries);
+    // the largest row capacity K that fits (beyond the widest pair nothing changes)
+    int64_t lo = 2, hi = std::max<int64_t>(2, cmax);
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (at(mid) <= max_entries)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    // the smallest threshold whose row capacity floor(1/t) + 1 is at most lo
+    float t = std::min(1.0f, (float)(1.0 / (double)lo));
+    while (t < 1.0f && std::floor(1.0 / (double)t) + 1.0 > (double)lo) t = std::nextafter(t, 2.0f);
+    float below = std::nextafter(t, 0.0f);
+    while (below > 0.0f && std::floor(1.0 / (double)below) + 1.0 <= (double)lo) {
+        t = below;
+        below = std::nextafter(t, 0.0f);
+    }
+    *thresh = t;
+    return QP_OK;
+}
+
 qp_status qp_set_tuning(const qp_tuning* t) {
     qp_tuning v{};
     if (!t) {
@@ -1103,8 +1188,20 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
         *out = r;
         return QP_OK;
     }
+    // sized to the output bound the run cannot overflow; that plan is taken
+    // while the bound is small next to the free device memory, otherwise the
+    // estimate (and, if it falls short, one more run with a fresh plan)
+    int64_t capacity = 0, bound = 0;
+    if (qp_output_bound(lens, n, pi, pj, np, thresh, &bound) == QP_OK) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            if (bound <= (int64_t)(free_b / 8) / 16) capacity = -1;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     qp_plan* pl = nullptr;
-    if ((st = qp_plan_create(lens, n, pi, pj, np, params, thresh, 0, &pl)) != QP_OK) return st;
+    if ((st = qp_plan_create(lens, n, pi, pj, np, params, thresh, capacity, &pl)) != QP_OK) return st;
     std::vector<int64_t> off(std::max(n, 1));
     int64_t tot = 0;
     for (int32_t i = 0; i < n; ++i) {

@@ -358,3 +358,35 @@ def test_tuned_class_map(B, params, shift):
                     k += 1
     finally:
         B.set_tuning(before["rows_per_lane"], before["waves_frac"])
+
+
+def test_plan_sized_to_output_bound(B, params):
+    """nnz_capacity = -1 sizes the plan to qp_output_bound: the partition
+    function alone (w = 0, whose flat posteriors need more than the library's
+    estimate) syncs without QP_ENOSPC, within the bound, matching the oracle."""
+    fam = W.c1_family()[:4]
+    pw = params.copy(w_hmm=0.0)
+    p = B.make_params(pw, 0)
+    lens = np.array([len(x) for x in fam], dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    hip = _hip()
+    d_seqs, d_off = _to_device(hip, np.concatenate(fam).astype(np.uint8)), _to_device(hip, off)
+    _say("plan sized to the output bound")
+    try:
+        plan = B.Plan(lens, p, 0.01, nnz_capacity=-1)
+        try:
+            plan.run(d_seqs.value, d_off.value, 0)
+            assert plan.sync_status() == B.QP_OK
+            res = plan.download()
+        finally:
+            plan.close()
+    finally:
+        for q in (d_seqs, d_off):
+            hip.hipFree(q)
+    assert res["nnz"] <= B.output_bound(lens, 0.01)
+    k = 0
+    for i in range(4):
+        for j in range(i + 1, 4):
+            orc = oracle.pair(fam[i], fam[j], pw, per_model=False)
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            k += 1
