@@ -83,6 +83,9 @@ def workload(name: str):
         fam = W.c3_family()
         return fam, None, "C3: 1,000 seqs, L log-uniform [50,1500], 499,500 pairs", W.c3_sample(
             [len(s) for s in fam])
+    if name == "nt":
+        fam = W.nt_workload_family()
+        return fam, None, "NT: 200 nucleotide seqs, L~U{250..350}, 19,900 pairs (alphabet 4)", W.c2_sample()
     if name == "c5p":
         ab = W.c5p_pairs()
         fam = [s for pair in ab for s in pair]
@@ -202,7 +205,7 @@ def main():
         return serve_stream(args, say)
 
     fam, pairs, desc, sample = workload(args.workload)
-    mp = W.make_params(0)
+    mp = W.make_nt_params(0) if args.workload == "nt" else W.make_params(0)
     prec = B.QP_FP64 if args.precision == "fp64" else B.QP_FP32_SCALED
     params = B.make_params(mp, prec)
     lens = np.array([len(s) for s in fam], dtype=np.int32)

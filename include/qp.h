@@ -96,6 +96,12 @@ typedef struct {
     double temperature;                  /* T                                */
     double w_hmm;                        /* weight of the HMM posterior      */
     int32_t precision;                   /* QP_FP32_SCALED or QP_FP64        */
+    int32_t alphabet;                    /* residue codes 0..alphabet-1: 20
+                                          * amino acids (0 reads as 20), 4
+                                          * nucleotides; 2..20.  joint and
+                                          * score keep their 20 x 20 layout;
+                                          * joint is 0 outside the
+                                          * alphabet x alphabet block       */
 } qp_params;
 
 /*

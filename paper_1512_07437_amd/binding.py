@@ -32,7 +32,7 @@ class qp_params(ctypes.Structure):
                 ("gap_open", ctypes.c_double * 2), ("gap_extend", ctypes.c_double * 2),
                 ("score", ctypes.c_double * 400), ("pf_gap_open", ctypes.c_double),
                 ("pf_gap_extend", ctypes.c_double), ("temperature", ctypes.c_double),
-                ("w_hmm", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("w_hmm", ctypes.c_double), ("precision", ctypes.c_int32), ("alphabet", ctypes.c_int32)]
 
 
 class qp_result(ctypes.Structure):
@@ -245,6 +245,7 @@ def make_params(mp, precision: int = QP_FP32_SCALED) -> qp_params:
     p.temperature = float(mp.temperature)
     p.w_hmm = float(mp.w_hmm)
     p.precision = int(precision)
+    p.alphabet = int(getattr(mp, "alphabet", 20))
     return p
 
 

@@ -50,6 +50,9 @@ qp_status fail(qp_status st, const char* fmt, ...) {
 // Most entries one row of a pair with c columns can keep: the posteriors of
 // a row sum to at most one, so at most floor(1/thresh) of them reach the
 // threshold; one more covers rounding (the kernels' per-row capacity).
+// residue codes of the parameters: 0..alphabet-1 (0 reads as 20)
+int alphabet_of(const qp_params* p) { return p->alphabet == 0 ? QP_ALPHA : p->alphabet; }
+
 int64_t row_bound(int32_t c, float thresh) {
     return (int64_t)std::min((double)c, std::floor(1.0 / (double)thresh) + 1.0);
 }
@@ -386,6 +389,7 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     dp.temperature = pl->params.temperature;
     dp.w_hmm = pl->params.w_hmm;
     dp.n_gap_classes = pl->params.n_gap_classes;
+    dp.alphabet = alphabet_of(&pl->params);
     HIP_TRY(hipMemcpy(pl->d_params, &dp, sizeof(dp), hipMemcpyHostToDevice));
 
     qp::PairArgs& a = pl->args;
@@ -430,7 +434,7 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
     hipEvent_t* ev = ev_set >= 0 ? pl->ev[ev_set] : nullptr;
     if (ev) HIP_TRY(record(ev[0], s, capturing));
     HIP_TRY(qp::launch_reset(pl->d_ints, pl->n_ints, s));
-    HIP_TRY(qp::launch_stage_seqs(pl->n, pl->in_seqs, pl->in_off, pl->d_lens, pl->d_seqa_off, pl->d_seqa,
+    HIP_TRY(qp::launch_stage_seqs(pl->n, alphabet_of(&pl->params), pl->in_seqs, pl->in_off, pl->d_lens, pl->d_seqa_off, pl->d_seqa,
                                   pl->d_ints + kIntFlags, s));
     HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->d_col0, pl->mmax, pl->fp64, s));
     HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
@@ -552,14 +556,21 @@ void qp_params_default(qp_params* p) {
     p->temperature = 5.0;
     p->w_hmm = 0.5;
     p->precision = QP_FP32_SCALED;
+    p->alphabet = QP_ALPHA;
 }
 
 qp_status qp_params_check(const qp_params* p) {
     if (!p) return fail(QP_EINVAL, "params is NULL");
+    const int A = alphabet_of(p);
+    if (A < 2 || A > QP_ALPHA) return fail(QP_EINVAL, "alphabet = %d is not in [2, %d]", p->alphabet, QP_ALPHA);
     double s = 0.0;
     for (int i = 0; i < QP_ALPHA * QP_ALPHA; ++i) {
         const double v = p->joint[i];
-        if (!(v > 0.0 && v < 1.0)) return fail(QP_EINVAL, "joint[%d] = %g is not in (0,1)", i, v);
+        if (i / QP_ALPHA < A && i % QP_ALPHA < A) {
+            if (!(v > 0.0 && v < 1.0)) return fail(QP_EINVAL, "joint[%d] = %g is not in (0,1)", i, v);
+        } else if (v != 0.0) {
+            return fail(QP_EINVAL, "joint[%d] = %g lies outside the %d-letter alphabet and must be 0", i, v, A);
+        }
         s += v;
         if (!std::isfinite(p->score[i])) return fail(QP_EINVAL, "score[%d] is not finite", i);
     }
@@ -1059,7 +1070,8 @@ qp_status qp_plan_sync(qp_plan* pl, qp_device_result* res) {
     }
     pl->last_nnz = nnz;
     trace("sync: done nnz=%lld flags=%d", (long long)nnz, flags);
-    if (flags & 4) return fail(QP_EINVAL, "a device sequence holds a residue code >= %d", QP_ALPHA);
+    if (flags & 4)
+        return fail(QP_EINVAL, "a device sequence holds a residue code >= %d", alphabet_of(&pl->params));
     if (flags & 2)
         return fail(QP_EDEVICE, "a row held more entries above the threshold than its staging capacity");
     if ((flags & 1) || nnz > pl->pool_cap) {
@@ -1170,14 +1182,15 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
     *out = nullptr;
     qp_status st = validate_lens(lens, n);
     if (st != QP_OK) return st;
+    if ((st = qp_params_check(params)) != QP_OK) return st;
     if (n > 0 && !seqs) return fail(QP_EINVAL, "seqs is NULL");
     for (int32_t i = 0; i < n; ++i) {
         if (!seqs[i]) return fail(QP_EINVAL, "seqs[%d] is NULL", i);
         for (int32_t c = 0; c < lens[i]; ++c)
-            if (seqs[i][c] >= QP_ALPHA)
-                return fail(QP_EINVAL, "seqs[%d][%d] = %d is not a residue code 0..19", i, c, seqs[i][c]);
+            if (seqs[i][c] >= alphabet_of(params))
+                return fail(QP_EINVAL, "seqs[%d][%d] = %d is not a residue code 0..%d", i, c, seqs[i][c],
+                            alphabet_of(params) - 1);
     }
-    if ((st = qp_params_check(params)) != QP_OK) return st;
     if (!(thresh > 0.0f && thresh <= 1.0f)) return fail(QP_EINVAL, "thresh = %g is not in (0, 1]", (double)thresh);
     const int64_t P = pi ? np : (int64_t)n * (n - 1) / 2;
     if (pi && np < 0) return fail(QP_EINVAL, "n_pairs < 0");

@@ -833,7 +833,7 @@ __global__ void k_tables(const DevParams* __restrict__ p, typename Pair2<T>::typ
         V2 v;
         v.x = T(0);
         v.y = T(0);
-        if (a < 20 && b < 20) {
+        if (a < p->alphabet && b < p->alphabet) {  // other codes never occur (zero weight)
             v.x = (T)(p->joint[a * 20 + b] / (qx[a] * qy[b]));
             v.y = (T)exp(p->score[a * 20 + b] / p->temperature);
         }
@@ -863,9 +863,10 @@ __global__ void k_reset(int* ints, int n) {
 
 __device__ __forceinline__ int64_t pair_start(int64_t i, int64_t n) { return i * n - i * (i + 1) / 2; }
 
-// 4-byte aligned, zero padded copy of every sequence; codes outside 0..19
-// are reported through bit 4 of *flags (and copied as the padding code)
-__global__ void k_stage_seqs(int32_t n, const uint8_t* __restrict__ seqs, const int64_t* __restrict__ seq_off,
+// 4-byte aligned, zero padded copy of every sequence; codes outside the
+// alphabet are reported through bit 4 of *flags (and copied as the padding
+// code)
+__global__ void k_stage_seqs(int32_t n, int32_t alphabet, const uint8_t* __restrict__ seqs, const int64_t* __restrict__ seq_off,
                              const int32_t* __restrict__ lens, const int64_t* __restrict__ seqa_off,
                              uint8_t* __restrict__ seqa, int* __restrict__ flags) {
     for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -874,8 +875,8 @@ __global__ void k_stage_seqs(int32_t n, const uint8_t* __restrict__ seqs, const 
         bool bad = false;
         for (int c = threadIdx.x; c < padded; c += blockDim.x) {
             const uint8_t v = c < len ? seqs[src + c] : (uint8_t)0;
-            bad |= v >= 20;
-            seqa[dst + c] = v >= 20 ? (uint8_t)kPadCode : v;  // keeps table reads in range
+            bad |= v >= alphabet;
+            seqa[dst + c] = v >= alphabet ? (uint8_t)kPadCode : v;  // keeps table reads in range
         }
         if (bad) atomicOr(flags, 4);
     }
@@ -1029,11 +1030,12 @@ hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, c
     return hipGetLastError();
 }
 
-hipError_t launch_stage_seqs(int32_t n, const uint8_t* seqs, const int64_t* seq_off, const int32_t* lens,
-                             const int64_t* seqa_off, uint8_t* seqa, int* flags, hipStream_t s) {
+hipError_t launch_stage_seqs(int32_t n, int32_t alphabet, const uint8_t* seqs, const int64_t* seq_off,
+                             const int32_t* lens, const int64_t* seqa_off, uint8_t* seqa, int* flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int blocks = n < 2048 ? n : 2048;
-    hipLaunchKernelGGL(k_stage_seqs, dim3(blocks), dim3(128), 0, s, n, seqs, seq_off, lens, seqa_off, seqa, flags);
+    hipLaunchKernelGGL(k_stage_seqs, dim3(blocks), dim3(128), 0, s, n, alphabet, seqs, seq_off, lens, seqa_off, seqa,
+                       flags);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct DevParams {
     double gap_extend[2];
     double pf_gap_open, pf_gap_extend, temperature, w_hmm;
     int32_t n_gap_classes;
+    int32_t alphabet;  // residue codes 0..alphabet-1
 };
 
 struct PairArgs {
@@ -98,7 +99,7 @@ struct PairArgs {
 // kernels launched by the host code (qp_device.hip)
 // copies each sequence to a 4-byte aligned slot of seqa (zero padded) and
 // sets bit 4 of *flags if a code is outside 0..19
-hipError_t launch_stage_seqs(int32_t n, const uint8_t* seqs, const int64_t* seq_off, const int32_t* lens,
+hipError_t launch_stage_seqs(int32_t n, int32_t alphabet, const uint8_t* seqs, const int64_t* seq_off, const int32_t* lens,
                              const int64_t* seqa_off, uint8_t* seqa, int* flags, hipStream_t s);
 hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, void* col0, int rows, int fp64,
                          hipStream_t s);

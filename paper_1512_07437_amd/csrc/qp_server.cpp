@@ -343,6 +343,11 @@ qp_status qp_server_submit(qp_server* s, const uint8_t* const* seqs, const int32
     if (!s || !ticket) return qp::set_error(QP_EINVAL, "server or ticket is NULL");
     *ticket = 0;
     if (n < 0 || (n > 0 && (!seqs || !lens))) return qp::set_error(QP_EINVAL, "bad family arguments");
+    {
+        const qp_status pst = qp_params_check(params);  // sets the message
+        if (pst != QP_OK) return pst;
+    }
+    const int alphabet = params->alphabet == 0 ? QP_ALPHA : params->alphabet;
     Request* r = new (std::nothrow) Request();
     if (!r) return qp::set_error(QP_ENOMEM, "out of host memory");
     r->t_submit = now_s();
@@ -360,7 +365,7 @@ qp_status qp_server_submit(qp_server* s, const uint8_t* const* seqs, const int32
     tot = 0;
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t c = 0; c < lens[i]; ++c)
-            if (seqs[i][c] >= QP_ALPHA) {
+            if (seqs[i][c] >= alphabet) {
                 delete r;
                 return qp::set_error(QP_EINVAL, "residue code out of range");
             }

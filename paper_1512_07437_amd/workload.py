@@ -42,6 +42,7 @@ class ModelParams:
     pf_gap_extend: float         # PF score of each further residue of a run
     temperature: float           # PF temperature T
     w_hmm: float = 0.5           # P = w*P_hmm + (1-w)*P_pf
+    alphabet: int = 20           # residue codes 0..alphabet-1 (4: nucleotides)
 
     @property
     def n_gap_classes(self) -> int:
@@ -114,7 +115,8 @@ def evolve(root: np.ndarray, rng: np.random.Generator, q: np.ndarray, subst: np.
     root = np.asarray(root, dtype=np.int64)
     # substitutions (inverse-CDF draw from the row of the old residue)
     cdf = np.cumsum(subst, axis=1)
-    cdf /= cdf[:, -1:]
+    tot = cdf[:, -1:]
+    cdf = np.divide(cdf, tot, out=np.zeros_like(cdf), where=tot > 0)  # rows of absent letters stay 0
     sub = rng.random(L) < r_sub
     u = rng.random(L)
     new = (cdf[root] > u[:, None]).argmax(axis=1)
@@ -157,12 +159,12 @@ def fit_length(seq: np.ndarray, target: int, rng: np.random.Generator, q: np.nda
 
 def make_family(n: int, lengths: Sequence[int], seed, *, r_sub: float = 0.3,
                 r_indel: float = 0.05, params: Optional[ModelParams] = None,
-                root_len: Optional[int] = None) -> List[np.ndarray]:
+                root_len: Optional[int] = None, subst: Optional[np.ndarray] = None) -> List[np.ndarray]:
     """A family of ``n`` sequences with the given target lengths, all evolved
     from one random root of length ``root_len`` (default: the longest target)."""
     params = params or make_params(0)
     q = background(params)
-    subst = substitution_matrix(0)
+    subst = substitution_matrix(0) if subst is None else subst
     rng = np.random.default_rng(seed)
     root_len = int(root_len or max(lengths))
     root = rng.choice(K, size=root_len, p=q).astype(np.uint8)
@@ -171,6 +173,61 @@ def make_family(n: int, lengths: Sequence[int], seed, *, r_sub: float = 0.3,
         leaf = evolve(root, rng, q, subst, r_sub, r_indel)
         fam.append(fit_length(leaf, int(lengths[t]), rng, q))
     return fam
+
+
+# --------------------------------------------------------------------------
+# nucleotide mode
+# --------------------------------------------------------------------------
+NT_ALPHABET = "ACGT"
+
+
+def make_nt_params(seed: int = 0, **kw) -> ModelParams:
+    """Nucleotide model (codes 0..3 = ACGT).  The nucleotide tables the
+    method names are not available; this stand-in applies the protein recipe
+    to four letters: A_ab ~ U(0,1), J = (A + A^T)/2 + 4 I, p = J / sum(J),
+    s_ab = round(2 log2(p_ab / (q_a q_b))), embedded in the 20 x 20 layout
+    with zeros outside the 4 x 4 block.  Gap and PF settings as for proteins
+    unless given."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 1.0, size=(4, 4))
+    j = (a + a.T) / 2.0 + 4.0 * np.eye(4)
+    p4 = j / j.sum()
+    q4 = p4.sum(axis=1)
+    joint = np.zeros((K, K))
+    joint[:4, :4] = p4
+    score = np.zeros((K, K))
+    score[:4, :4] = np.round(2.0 * np.log2(p4 / np.outer(q4, q4)))
+    d = dict(gap_open=(0.02, 0.005), gap_extend=(0.5, 0.9), pf_gap_open=-12.0, pf_gap_extend=-1.0,
+             temperature=5.0, w_hmm=0.5)
+    d.update(kw)
+    return ModelParams(joint=joint, gap_open=tuple(d["gap_open"]), gap_extend=tuple(d["gap_extend"]), score=score,
+                       pf_gap_open=float(d["pf_gap_open"]), pf_gap_extend=float(d["pf_gap_extend"]),
+                       temperature=float(d["temperature"]), w_hmm=float(d["w_hmm"]), alphabet=4)
+
+
+def nt_substitution_matrix(seed: int = 0) -> np.ndarray:
+    """Row-stochastic 4 x 4 substitution kernel with zero diagonal (rows
+    Dirichlet(1) over the three other letters), in the 20 x 20 layout."""
+    rng = np.random.default_rng(seed)
+    rng.uniform(0.0, 1.0, size=(4, 4))  # advance past the joint draw
+    r = np.zeros((K, K))
+    for a in range(4):
+        r[a, [b for b in range(4) if b != a]] = rng.dirichlet(np.ones(3))
+    return r
+
+
+def nt_family(n: int, lengths: Sequence[int], seed, *, r_sub: float = 0.3, r_indel: float = 0.05) -> List[np.ndarray]:
+    """Nucleotide family: the evolution model of the protein families over
+    the four letters of the nucleotide model."""
+    return make_family(n, lengths, seed, r_sub=r_sub, r_indel=r_indel, params=make_nt_params(0),
+                       subst=nt_substitution_matrix(0))
+
+
+def nt_workload_family() -> List[np.ndarray]:
+    """200 nucleotide sequences, lengths U{250..350}, seed 6 (the C2 shape)."""
+    rng = np.random.default_rng(6)
+    lens = rng.integers(250, 351, size=200)
+    return nt_family(200, lens, np.random.SeedSequence(6))
 
 
 # --------------------------------------------------------------------------

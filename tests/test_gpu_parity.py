@@ -390,3 +390,17 @@ def test_plan_sized_to_output_bound(B, params):
             orc = oracle.pair(fam[i], fam[j], pw, per_model=False)
             _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
             k += 1
+
+
+def test_nucleotide_family(B):
+    """Nucleotide mode (alphabet 4) on the device against the oracle."""
+    mp = W.make_nt_params(0)
+    fam = W.nt_family(7, [60, 120, 200, 300, 450, 700, 90], 8)
+    _say("nucleotide family")
+    res = B.qp_posteriors(fam, B.make_params(mp, 0), 0.01)
+    k = 0
+    for i in range(len(fam)):
+        for j in range(i + 1, len(fam)):
+            orc = oracle.pair(fam[i], fam[j], mp, per_model=False)
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            k += 1
