@@ -307,6 +307,17 @@ def main():
         "pair_kernels": classes,
         "all_classes_tflops": round(cells * FLOP_PER_CELL / (kernel_ms * 1e-3) / 1e12, 3) if kernel_ms > 0 else None,
     }
+    if args.workload in ("c2", "nt"):
+        # the host-to-host path (qp_posteriors: staging of the sequences, a
+        # plan, the run, the CSR copied back into pinned host memory), after
+        # the timed region; the first call warms the library's host pools
+        B.qp_posteriors(fam, params, args.thresh)
+        t_e = time.perf_counter()
+        e2e = B.qp_posteriors(fam, params, args.thresh)
+        e2e_s = time.perf_counter() - t_e
+        out["end_to_end"] = {"ms": round(e2e_s * 1e3, 2), "gcups": round(cells / e2e_s / 1e9, 2),
+                             "nnz": int(e2e["nnz"]), "what": "qp_posteriors, host sequences in, host CSR out"}
+        del e2e
     if pairs is None and len(fam) > 1:
         # the next stage on the host: guide tree and tree-guided distances
         t_gt = time.perf_counter()
