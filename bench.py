@@ -75,7 +75,7 @@ def workload(name: str):
     from paper_1512_07437_amd import workload as W
     if name == "c1":
         fam = W.c1_family()
-        return fam, None, "C1: 8 seqs, L~U{80..120}, 28 pairs", None
+        return fam, None, "C1: 8 seqs, L~U{80..120}, 28 pairs", np.arange(28)
     if name == "c2":
         fam = W.c2_family()
         return fam, None, "C2: 200 seqs, L~U{250..350}, 19,900 pairs", W.c2_sample()
@@ -364,6 +364,10 @@ def serve_stream(args, say):
     results = [None] * len(stream)
 
     failed = []
+    # oracle spot checks: every check_every-th family keeps its result, and two
+    # seeded pairs of each are compared with the FP64 oracle after the run
+    check_every = max(1, len(stream) // 10)
+    kept = {}
 
     def waiter():
         for k in range(len(stream)):
@@ -372,6 +376,8 @@ def serve_stream(args, say):
             try:
                 res, tm = srv.wait(tickets[k])
                 results[k] = (res["n_pairs"], res["nnz"], tm)
+                if k % check_every == 0:
+                    kept[k] = res  # spot-checked against the oracle after the stream
             except B.QpError as e:  # e.g. QP_ENOSPC: reported, not retried
                 failed.append((k, str(e)))
 
@@ -425,6 +431,25 @@ def serve_stream(args, say):
         "offered_gcups": round(cells / (stream[-1][0] + 1e-9) / 1e9, 3),
         "wall_s": round(t_end - t0, 2),
     }
+    if kept and not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(44)
+        worst = ea_worst = 0.0
+        n_checked = 0
+        for k, res in sorted(kept.items()):
+            fam = stream[k][1]
+            n = len(fam)
+            for p in rng.choice(n * (n - 1) // 2, 2, replace=False):
+                i, j = W.pair_of_index(int(p), n)
+                r = oracle.pair(fam[i], fam[j], mp, per_model=False)
+                rp, col, val = B.pair_csr(res, int(p))
+                rows = np.repeat(np.arange(len(fam[i])), np.diff(rp))
+                worst = max(worst, float(np.abs(val.astype(np.float64) - r["post"][rows, col]).max(initial=0.0)))
+                ea_worst = max(ea_worst, abs((1.0 - res["dist"][int(p)]) - r["ea"]))
+                n_checked += 1
+        out["max_abs_err_vs_oracle"] = worst
+        out["max_abs_ea_err_vs_oracle"] = ea_worst
+        out["oracle_checked_pairs"] = "%d seeded pairs of %d served families" % (n_checked, len(kept))
     print(json.dumps(out), flush=True)
 
 
