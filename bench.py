@@ -183,6 +183,7 @@ def main():
     ap.add_argument("--no-per-pair", action="store_true", help="skip the plain per-pair form's measurement")
     ap.add_argument("--families", type=int, default=200, help="c4: families replayed")
     ap.add_argument("--slots", type=int, default=8, help="c4: families in flight")
+    ap.add_argument("--rate", type=float, default=20.0, help="c4: mean arrivals per second")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -353,7 +354,7 @@ def serve_stream(args, say):
     mp = W.make_params(0)
     params = B.make_params(mp)
     stream = []
-    for t_arr, fam in W.c4_stream(args.families):
+    for t_arr, fam in W.c4_stream(args.families, rate=args.rate):
         stream.append((t_arr, fam))
         if len(stream) % 200 == 0:
             say("generated %d families" % len(stream))
@@ -417,7 +418,7 @@ def serve_stream(args, say):
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": "C4: Poisson stream, mean 20 families/s, k~U{10..500}, L~U{100..600}",
+        "config": {"workload": "C4: Poisson stream, mean %g families/s, k~U{10..500}, L~U{100..600}" % args.rate,
                    "families": len(stream), "failed_families": len(failed), "slots": args.slots,
                    "cells": int(cells), "pairs": int(sum(r[0] for r in done))},
         "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),

@@ -273,16 +273,16 @@ def c3_sample(lens: Sequence[int]) -> np.ndarray:
     return np.sort(np.concatenate([uni, big]))
 
 
-def c4_stream(n_families: int = 2000, seed: int = 4):
-    """Poisson stream of families: exponential inter-arrivals (mean 50 ms),
-    sizes U{10..500}, lengths U{100..600}, each family from its own root.
-    Yields (arrival_seconds, family)."""
+def c4_stream(n_families: int = 2000, seed: int = 4, rate: float = 20.0):
+    """Poisson stream of families: exponential inter-arrivals (mean 1/rate,
+    50 ms by default), sizes U{10..500}, lengths U{100..600}, each family
+    from its own root.  Yields (arrival_seconds, family)."""
     ss = np.random.SeedSequence(seed)
     rng = np.random.default_rng(ss)
     children = ss.spawn(n_families)
     t = 0.0
     for f in range(n_families):
-        t += float(rng.exponential(0.05))
+        t += float(rng.exponential(1.0 / rate))
         frng = np.random.default_rng(children[f])
         k = int(frng.integers(10, 501))
         lens = frng.integers(100, 601, size=k)
