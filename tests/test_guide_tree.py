@@ -146,3 +146,59 @@ def test_library_edge_cases_and_errors(B):
         B.tree_distance(np.array([[0, 1], [2, 5]]), 3)  # 5 does not exist yet
     assert e.value.status == B.QP_EINVAL
     assert B.lib.qp_guide_tree(None, 0, None, None) == B.QP_EINVAL
+
+
+# --------------------------------------------- planted mistakes in the oracle
+def _linkage(dist, n, rule):
+    """The oracle's join loop with another merge rule (a planted mistake)."""
+    D = {}
+    for i in range(n):
+        for j in range(i + 1, n):
+            D[(i, j)] = float(dist[T.pair_index(i, j, n)])
+    size = {i: 1 for i in range(n)}
+
+    def get(a, b):
+        return D[(a, b)] if a < b else D[(b, a)]
+
+    active = list(range(n))
+    joins, heights = [], []
+    for step in range(n - 1):
+        d, a, b = min((get(a, b), a, b) for a in active for b in active if a < b)
+        made = n + step
+        for x in active:
+            if x != a and x != b:
+                D[(x, made)] = rule(get(a, x), get(b, x), size[a], size[b])
+        size[made] = size[a] + size[b]
+        active.remove(a)
+        active.remove(b)
+        active.append(made)
+        joins.append((a, b))
+        heights.append(d / 2.0)
+    return joins, heights
+
+
+@pytest.mark.parametrize("name,rule", [
+    ("size-weighted mean (UPGMA)", lambda da, db, na, nb: (na * da + nb * db) / (na + nb)),
+    ("single linkage", lambda da, db, na, nb: min(da, db)),
+    ("complete linkage", lambda da, db, na, nb: max(da, db)),
+    ("mean without halving", lambda da, db, na, nb: da + db),
+])
+def test_hand_example_catches_other_merge_rules(name, rule):
+    """Each plausible wrong merge rule changes the hand-worked heights."""
+    M = [[0, 2, 4, 10], [2, 0, 4, 10], [4, 4, 0, 6], [10, 10, 6, 0]]
+    _, heights = _linkage(_condensed(M), 4, rule)
+    assert heights != [1.0, 2.0, 4.0], name
+    _, ok = _linkage(_condensed(M), 4, lambda da, db, na, nb: (da + db) / 2.0)
+    assert ok == [1.0, 2.0, 4.0]
+
+
+def test_caterpillar_catches_counting_only_sequences():
+    """Counting the sequences under the common join instead of all its nodes
+    (or the path between the two) gives other numbers on the chain."""
+    n = 7
+    joins = [(0, 1)] + [(k, n + k - 2) for k in range(2, n)]
+    td = T.tree_distance(joins, n)
+    leaves_only = [2 if j == 1 else j + 1 for j in range(1, n)]
+    path_nodes = [3] + [j + 2 for j in range(2, n)]  # 0 .. up to the join .. down to j
+    got = [td[T.pair_index(0, j, n)] for j in range(1, n)]
+    assert got != leaves_only and got != path_nodes
