@@ -862,6 +862,30 @@ __global__ void k_reset(int* ints, int n) {
 }
 
 __device__ __forceinline__ int64_t pair_start(int64_t i, int64_t n) { return i * n - i * (i + 1) / 2; }
+// counter[k] += 1 for every lane with `valid`, with one atomic per distinct k
+// in the wavefront (the lanes of a wave mostly share a key, so per-lane
+// atomics on a few addresses would serialise); returns the lane's 0-based
+// position among all additions to counter[k].  Uniform control flow: every
+// lane of the wave must call it.
+__device__ __forceinline__ int wave_count_add(int* counter, int k, bool valid) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    unsigned long long todo = __ballot(valid);
+    int slot = 0;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int lk = __shfl(k, leader, kWave);
+        const bool mine = valid && k == lk;
+        const unsigned long long same = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counter[lk], __popcll(same));
+        base = __shfl(base, leader, kWave);
+        if (mine) slot = base + __popcll(same & below);
+        todo &= ~same;
+    }
+    return slot;
+}
+
 
 // 4-byte aligned, zero padded copy of every sequence; codes outside the
 // alphabet are reported through bit 4 of *flags (and copied as the padding
@@ -891,29 +915,32 @@ __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32
         rows1[P] = 0;
         pair_nnz[P] = 0;
     }
-    if (p >= P) return;
-    int64_t i, j;
-    if (list_i) {
-        i = list_i[p];
-        j = list_j[p];
-    } else {
-        const double nn = (double)n;
-        const double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)p;
-        i = (int64_t)floor((2.0 * nn - 1.0 - sqrt(disc > 0 ? disc : 0.0)) / 2.0);
-        if (i < 0) i = 0;
-        while (i > 0 && pair_start(i, n) > p) --i;
-        while (i + 1 < n && pair_start(i + 1, n) <= p) ++i;
-        j = p - pair_start(i, n) + i + 1;
+    // lanes past the pair list take part in the wave-wide count only
+    int kk = 0;
+    if (p < P) {
+        int64_t i, j;
+        if (list_i) {
+            i = list_i[p];
+            j = list_j[p];
+        } else {
+            const double nn = (double)n;
+            const double disc = (2.0 * nn - 1.0) * (2.0 * nn - 1.0) - 8.0 * (double)p;
+            i = (int64_t)floor((2.0 * nn - 1.0 - sqrt(disc > 0 ? disc : 0.0)) / 2.0);
+            if (i < 0) i = 0;
+            while (i > 0 && pair_start(i, n) > p) --i;
+            while (i + 1 < n && pair_start(i + 1, n) <= p) ++i;
+            j = p - pair_start(i, n) + i + 1;
     }
-    pi[p] = (int32_t)i;
-    pj[p] = (int32_t)j;
-    const int64_t m = lens[i], c = lens[j];
-    rows1[p] = m + 1;
-    int cb = (int)(log2((double)(m * c)) * 2.0);
-    cb = cb < 0 ? 0 : (cb >= kCostBins ? kCostBins - 1 : cb);
-    const int kk = pair_class((int)m, map) * kCostBins + cb;
-    key[p] = kk;
-    atomicAdd(&hist[kk], 1);
+        pi[p] = (int32_t)i;
+        pj[p] = (int32_t)j;
+        const int64_t m = lens[i], c = lens[j];
+        rows1[p] = m + 1;
+        int cb = (int)(log2((double)(m * c)) * 2.0);
+        cb = cb < 0 ? 0 : (cb >= kCostBins ? kCostBins - 1 : cb);
+        kk = pair_class((int)m, map) * kCostBins + cb;
+        key[p] = kk;
+    }
+    wave_count_add(hist, kk, p < P);
 }
 
 // exclusive offsets of the cost classes, most expensive class first
@@ -934,10 +961,10 @@ __global__ void k_bins(const int* __restrict__ hist, int* __restrict__ bin_start
 __global__ void k_fill_queue(int64_t P, const int32_t* __restrict__ key, const int* __restrict__ bin_start,
                              int* __restrict__ bin_fill, int32_t* __restrict__ queue) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const int kk = key[p];
-    const int slot = bin_start[kk] + atomicAdd(&bin_fill[kk], 1);
-    queue[slot] = (int32_t)p;
+    const bool valid = p < P;
+    const int kk = valid ? key[p] : 0;
+    const int rank = wave_count_add(bin_fill, kk, valid);
+    if (valid) queue[bin_start[kk] + rank] = (int32_t)p;
 }
 
 // ------------------------------------------------------ int64 scan
