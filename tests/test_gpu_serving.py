@@ -115,3 +115,30 @@ def test_cancel_and_poll(B, params):
             assert e.value.status == B.QP_ECANCELED
     finally:
         srv.close()
+
+
+def test_mixed_models_in_one_stream(B, params):
+    """Requests carry their own parameters: protein FP32, protein FP64 and
+    nucleotide families served side by side each equal their direct run bit
+    for bit, and a pair of each meets the oracle at its precision's bar."""
+    import oracle
+    nt = W.make_nt_params(0)
+    jobs = [("protein fp32", _families()[0], params, 0, 1e-5),
+            ("protein fp64", _families()[1], params, 1, 1e-7),
+            ("nucleotide fp32", W.nt_family(9, [80, 150, 220, 300, 120, 90, 260, 200, 140], 77), nt, 0, 1e-5),
+            ("protein fp32 again", _families()[2], params, 0, 1e-5)]
+    srv = B.Server(hbm_budget_bytes=32 << 30, max_slots=4, n_streams=4)
+    try:
+        tickets = [srv.submit(fam, B.make_params(mp, prec), 0.01) for _, fam, mp, prec, _ in jobs]
+        served = [srv.wait(t, timeout_ms=120000)[0] for t in tickets]
+    finally:
+        srv.close()
+    for (name, fam, mp, prec, tol), res in zip(jobs, served):
+        _say("mixed stream:", name)
+        direct = B.qp_posteriors(fam, B.make_params(mp, prec), 0.01)
+        for key in KEYS:
+            assert np.array_equal(direct[key], res[key]), (name, key)
+        orc = oracle.pair(fam[0], fam[1], mp, per_model=False)
+        rp, col, val = B.pair_csr(res, 0)
+        rows = np.repeat(np.arange(len(fam[0])), np.diff(rp))
+        assert np.abs(val.astype(np.float64) - orc["post"][rows, col]).max(initial=0.0) <= tol, name
