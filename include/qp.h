@@ -127,6 +127,9 @@ typedef struct {
     double* dist;           /* [n_pairs] 1 - EA                               */
     double* log_z;          /* [2 * n_pairs] log Z_hmm, log Z_pf per pair     */
     double device_ms;       /* device time of the posterior pipeline          */
+    float thresh;           /* sparsity threshold the entries were kept at
+                               (the requested one; a served family admitted
+                               under a memory budget may have a larger one)  */
 } qp_result;
 
 /* Library version, (major << 16) | minor. */
@@ -154,7 +157,12 @@ qp_status qp_params_check(const qp_params* p);
  *   thresh    sparsity threshold in (0, 1]
  *   out       receives a library-owned result on QP_OK, NULL otherwise
  * Runs on the current HIP device on an internal stream and blocks until the
- * result is on the host.
+ * result is on the host.  Every plan it makes holds the guaranteed output
+ * bound of its pairs (see qp_output_bound), so no run can overflow and none
+ * is repeated; when the bound of the whole family exceeds a third of the
+ * free device memory, the pairs are cut in order into chunks whose bounds
+ * fit, run one after the other, and concatenated into one result.
+ * QP_ENOMEM if a single pair's bound cannot be held.
  */
 qp_status qp_posteriors(const uint8_t* const* seqs, const int32_t* lens, int32_t n,
                         const qp_params* params, float thresh, qp_result** out);

@@ -42,7 +42,7 @@ class qp_result(ctypes.Structure):
                 ("row_ptr", ctypes.POINTER(ctypes.c_int32)), ("nnz_off", ctypes.POINTER(ctypes.c_int64)),
                 ("col", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_float)),
                 ("dist", ctypes.POINTER(ctypes.c_double)), ("log_z", ctypes.POINTER(ctypes.c_double)),
-                ("device_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("thresh", ctypes.c_float)]
 
 
 class qp_device_result(ctypes.Structure):
@@ -298,6 +298,7 @@ def _take_result(out) -> Dict[str, np.ndarray]:
         r = out.contents
         P, rows, nnz = r.n_pairs, r.total_rows, r.nnz
         return dict(n_seqs=int(r.n_seqs), n_pairs=int(P), nnz=int(nnz), device_ms=float(r.device_ms),
+                    thresh=float(r.thresh),
                     pair_i=_view(owner, r.pair_i, P, np.int32), pair_j=_view(owner, r.pair_j, P, np.int32),
                     row_off=_view(owner, r.row_off, P + 1, np.int64),
                     row_ptr=_view(owner, r.row_ptr, rows, np.int32),

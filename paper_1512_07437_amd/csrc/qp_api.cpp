@@ -489,6 +489,13 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
 }
 
 static qp_status capture_graphs(qp_plan* pl) {
+    // a launch of these graphs may still be in flight: it ends before any of
+    // them goes (runs of a plan are ordered one after the other, so the last
+    // run's end covers every earlier one)
+    if (pl->ran && pl->last_g >= 0) {
+        hipError_t e = hipEventSynchronize(pl->ev[pl->last_g][3]);
+        if (e != hipSuccess) return fail(QP_EDEVICE, "waiting for the previous run: %s", hipGetErrorString(e));
+    }
     for (int g = 0; g < kNumEventSets; ++g) {
         if (pl->exec[g]) {
             hipGraphExecDestroy(pl->exec[g]);
@@ -750,6 +757,7 @@ qp_status qp::plan_download(qp_plan* pl, qp_result** out, qp::Staging* stg) {
     const int64_t P = pl->P;
     qp_result* r = qp::result_alloc(pl->n, P, pl->total_rows, d.nnz);
     if (!r) return fail(QP_ENOMEM, "out of host memory");
+    r->thresh = pl->thresh;
     if (P == 0) {
         *out = r;
         return QP_OK;
@@ -811,6 +819,7 @@ qp_status qp::plan_download(qp_plan* pl, qp_result** out, qp::Staging* stg) {
     }
     collect_timing(pl);
     r->device_ms = pl->n_timed ? pl->sum_pipe_ms / pl->n_timed : 0.0;
+    r->thresh = pl->thresh;
     *out = r;
     return QP_OK;
 }
@@ -891,6 +900,9 @@ qp_status qp_plan_run(qp_plan* pl, const uint8_t* d_seqs, const int64_t* d_seq_o
         HIP_TRY(hipEventSynchronize(pl->ev[g][3]));
         collect_timing(pl);
     }
+    // a run on another stream than the previous one starts after it: both
+    // use the same workspace and outputs
+    if (pl->ran && pl->last_g >= 0 && s != pl->last_stream) HIP_TRY(hipStreamWaitEvent(s, pl->ev[pl->last_g][3], 0));
     pl->in_seqs = d_seqs;
     pl->in_off = d_seq_off;
     pl->last_stream = s;
@@ -1198,23 +1210,60 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
         // nothing to compute: an empty result, without touching the device
         qp_result* r = qp::result_alloc(n, 0, 0, 0);
         if (!r) return fail(QP_ENOMEM, "out of host memory");
+        r->thresh = thresh;
         *out = r;
         return QP_OK;
     }
-    // sized to the output bound the run cannot overflow; that plan is taken
-    // while the bound is small next to the free device memory, otherwise the
-    // estimate (and, if it falls short, one more run with a fresh plan)
-    int64_t capacity = 0, bound = 0;
-    if (qp_output_bound(lens, n, pi, pj, np, thresh, &bound) == QP_OK) {
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-            if (bound <= (int64_t)(free_b / 8) / 16) capacity = -1;
-        } else {
-            (void)hipGetLastError();
-        }
+    // Every plan is sized to the guaranteed output bound of its pairs, so no
+    // run can overflow its sparse output and nothing is ever re-run.  When
+    // the bound of the whole family does not fit a share of the free device
+    // memory, the pairs are cut, in order, into chunks whose bounds do; the
+    // chunks run one after the other and their results are concatenated.
+    {
+        int64_t bound = 0;  // validates the pair list before any device call
+        if ((st = qp_output_bound(lens, n, pi, pj, np, thresh, &bound)) != QP_OK) return st;
     }
-    qp_plan* pl = nullptr;
-    if ((st = qp_plan_create(lens, n, pi, pj, np, params, thresh, capacity, &pl)) != QP_OK) return st;
+    int dev = 0;
+    if ((st = check_device(&dev, nullptr)) != QP_OK) return st;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QP_EDEVICE, "hipMemGetInfo failed");
+    }
+    // pool and gathered output: 16 bytes per entry; a third of the free
+    // memory leaves the rest to the per-wave workspace
+    const int64_t max_entries = std::max<int64_t>(1, (int64_t)(free_b / 3) / 16);
+    std::vector<int32_t> ci, cj;  // explicit pair list of every chunk
+    std::vector<int64_t> cut{0};  // chunk k = pairs cut[k] .. cut[k+1]-1
+    {
+        try {
+            ci.reserve((size_t)P);
+            cj.reserve((size_t)P);
+        } catch (const std::bad_alloc&) {
+            return fail(QP_ENOMEM, "out of host memory");
+        }
+        int64_t acc = 0;
+        auto add = [&](int32_t a, int32_t b) {
+            const int64_t bp = (int64_t)lens[a] * row_bound(lens[b], thresh);
+            if (acc > 0 && acc + bp > max_entries) {
+                cut.push_back((int64_t)ci.size());
+                acc = 0;
+            }
+            acc += bp;
+            ci.push_back(a);
+            cj.push_back(b);
+        };
+        if (pi) {
+            for (int64_t k = 0; k < np; ++k) add(pi[k], pj[k]);
+        } else {
+            for (int32_t i = 0; i + 1 < n; ++i)
+                for (int32_t j = i + 1; j < n; ++j) add(i, j);
+        }
+        cut.push_back(P);
+    }
+    const int n_chunks = (int)cut.size() - 1;
+    trace("host: %lld pairs in %d chunk(s) of at most %lld bound entries", (long long)P, n_chunks,
+          (long long)max_entries);
     std::vector<int64_t> off(std::max(n, 1));
     int64_t tot = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -1225,12 +1274,12 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
     uint8_t* d = nullptr;
     int64_t* d_off = nullptr;
     hipStream_t s = nullptr;
+    std::vector<qp_result*> parts((size_t)n_chunks, nullptr);
     auto cleanup = [&]() {
         if (s) hipStreamSynchronize(s);
         if (h) hipHostFree(h);
         if (d) hipFree(d);
         if (d_off) hipFree(d_off);
-        qp_plan_destroy(pl);
         if (s) hipStreamDestroy(s);
     };
     hipError_t e = hipHostMalloc((void**)&h, (size_t)std::max<int64_t>(tot, 1), hipHostMallocDefault);
@@ -1238,6 +1287,7 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
     if (e == hipSuccess) e = hipMalloc((void**)&d_off, sizeof(int64_t) * std::max(n, 1));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         cleanup();
         return fail(QP_ENOMEM, "device staging allocation failed: %s", hipGetErrorString(e));
     }
@@ -1250,23 +1300,67 @@ static qp_status run_host(const uint8_t* const* seqs, const int32_t* lens, int32
         cleanup();
         return fail(QP_EDEVICE, "host-to-device copy failed: %s", hipGetErrorString(e));
     }
-    st = qp_plan_run(pl, d, d_off, s);
-    if (st == QP_OK) st = qp_plan_download(pl, out);
-    if (st == QP_ENOSPC) {
-        // the sparse output outgrew the estimate: one more run with a fresh
-        // plan sized to what the first run produced
-        const int64_t need = pl->last_nnz + 1024;
-        trace("host: retry with capacity %lld", (long long)need);
-        hipStreamSynchronize(s);
-        qp_plan_destroy(pl);
-        pl = nullptr;
-        st = qp_plan_create(lens, n, pi, pj, np, params, thresh, need, &pl);
+    for (int k = 0; k < n_chunks && st == QP_OK; ++k) {
+        const int64_t c0 = cut[k], cn = cut[k + 1] - cut[k];
+        qp_plan* pl = nullptr;
+        // one chunk covering all pairs of an all-pairs family keeps the
+        // implicit pair list
+        const bool implicit = !pi && n_chunks == 1;
+        st = qp_plan_create(lens, n, implicit ? nullptr : ci.data() + c0, implicit ? nullptr : cj.data() + c0,
+                            implicit ? 0 : cn, params, thresh, -1, &pl);
         if (st == QP_OK) st = qp_plan_run(pl, d, d_off, s);
-        if (st == QP_OK) st = qp_plan_download(pl, out);
+        if (st == QP_OK) st = qp_plan_download(pl, &parts[k]);
+        if (pl) {
+            std::string keep = g_err;
+            qp_plan_destroy(pl);
+            g_err = keep;
+        }
     }
     std::string keep = g_err;
     cleanup();
     g_err = keep;
+    if (st == QP_OK && n_chunks == 1) {
+        *out = parts[0];
+        parts[0] = nullptr;
+    } else if (st == QP_OK) {
+        // concatenate the chunks in pair order
+        int64_t rows = 0, nnz = 0;
+        for (qp_result* r : parts) {
+            rows += r->total_rows;
+            nnz += r->nnz;
+        }
+        qp_result* all = qp::result_alloc(n, P, rows, nnz);
+        if (!all) {
+            st = fail(QP_ENOMEM, "out of host memory for the concatenated result");
+        } else {
+            int64_t p0 = 0, r0 = 0, z0 = 0;
+            double ms = 0.0;
+            for (qp_result* r : parts) {
+                const int64_t cp = r->n_pairs;
+                std::memcpy(all->pair_i + p0, r->pair_i, sizeof(int32_t) * cp);
+                std::memcpy(all->pair_j + p0, r->pair_j, sizeof(int32_t) * cp);
+                for (int64_t q = 0; q < cp; ++q) {
+                    all->row_off[p0 + q] = r0 + r->row_off[q];
+                    all->nnz_off[p0 + q] = z0 + r->nnz_off[q];
+                }
+                std::memcpy(all->row_ptr + r0, r->row_ptr, sizeof(int32_t) * r->total_rows);
+                std::memcpy(all->col + z0, r->col, sizeof(int32_t) * r->nnz);
+                std::memcpy(all->val + z0, r->val, sizeof(float) * r->nnz);
+                std::memcpy(all->dist + p0, r->dist, sizeof(double) * cp);
+                std::memcpy(all->log_z + 2 * p0, r->log_z, sizeof(double) * 2 * cp);
+                p0 += cp;
+                r0 += r->total_rows;
+                z0 += r->nnz;
+                ms += r->device_ms;
+            }
+            all->row_off[P] = r0;
+            all->nnz_off[P] = z0;
+            all->device_ms = ms;
+            all->thresh = thresh;
+            *out = all;
+        }
+    }
+    for (qp_result* r : parts) qp_result_free(r);
     return st;
 }
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -33,71 +34,67 @@ double now_s() {
 
 enum class St { Queued, Running, Completing, Done, Canceled };
 
-// Device blocks freed by finished families are kept for later ones (best fit
-// within twice the request), so the loop does not hand memory back to the
-// runtime while other families run.  Blocks are rounded to 64 KiB.
-struct DevCache {
+// Device memory of the server: one region of the whole budget, reserved when
+// the server is made, from which every admitted family takes one contiguous
+// block of the size computed for it at submit (first fit; freed blocks merge
+// with their neighbours).  Serving then makes no hipMalloc or hipFree call:
+// those synchronise the device and would stall the families in flight.
+struct Arena {
     std::mutex mu;
-    std::multimap<size_t, void*> idle;       // size -> block
-    std::map<void*, size_t> owned;           // every block we allocated
-    int64_t idle_bytes = 0;
-    int64_t limit = 0;                       // idle bytes kept at most
+    char* base = nullptr;
+    int64_t size = 0;
+    std::map<int64_t, int64_t> free_;  // offset -> length of each free range
+    int64_t in_use = 0;
 
+    static int64_t round(int64_t b) { return (std::max<int64_t>(b, 1) + 255) & ~int64_t(255); }
+    // offset of a block of `bytes`, or -1 when no free range holds it
+    int64_t take(int64_t bytes) {
+        bytes = round(bytes);
+        std::lock_guard<std::mutex> g(mu);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const int64_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes) free_[off + bytes] = len - bytes;
+            in_use += bytes;
+            return off;
+        }
+        return -1;
+    }
+    void give(int64_t off, int64_t bytes) {
+        bytes = round(bytes);
+        std::lock_guard<std::mutex> g(mu);
+        in_use -= bytes;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+};
+
+// a family's block, handed out piece by piece (256-byte aligned, the same
+// rounding the plan's size count uses); pieces go back with the block
+struct Bump {
+    char* base = nullptr;
+    int64_t used = 0, cap = 0;
     static void* alloc(void* ctx, size_t bytes) {
-        DevCache* c = static_cast<DevCache*>(ctx);
-        const size_t need = (std::max<size_t>(bytes, 1) + 65535) & ~(size_t)65535;
-        {
-            std::lock_guard<std::mutex> g(c->mu);
-            auto it = c->idle.lower_bound(need);
-            if (it != c->idle.end() && it->first <= 2 * need) {
-                void* p = it->second;
-                c->idle_bytes -= (int64_t)it->first;
-                c->idle.erase(it);
-                return p;
-            }
-        }
-        void* p = nullptr;
-        if (hipMalloc(&p, need) != hipSuccess) {
-            (void)hipGetLastError();
-            c->trim(0);  // give the idle blocks back and try once more
-            if (hipMalloc(&p, need) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
-        }
-        std::lock_guard<std::mutex> g(c->mu);
-        c->owned[p] = need;
+        Bump* b = static_cast<Bump*>(ctx);
+        const int64_t need = Arena::round((int64_t)bytes);
+        if (b->used + need > b->cap) return nullptr;
+        void* p = b->base + b->used;
+        b->used += need;
         return p;
     }
-    static void release(void* ctx, void* p) {
-        DevCache* c = static_cast<DevCache*>(ctx);
-        {
-            std::lock_guard<std::mutex> g(c->mu);
-            auto it = c->owned.find(p);
-            if (it == c->owned.end()) return;
-            c->idle.emplace(it->second, p);
-            c->idle_bytes += (int64_t)it->second;
-        }
-        if (c->idle_bytes > c->limit) c->trim(c->limit / 2);
-    }
-    // free idle blocks (largest first) until at most `keep` bytes stay idle
-    void trim(int64_t keep) {
-        std::lock_guard<std::mutex> g(mu);
-        while (idle_bytes > keep && !idle.empty()) {
-            auto it = std::prev(idle.end());
-            hipFree(it->second);
-            owned.erase(it->second);
-            idle_bytes -= (int64_t)it->first;
-            idle.erase(it);
-        }
-    }
-    void free_all() {
-        std::lock_guard<std::mutex> g(mu);
-        for (auto& kv : owned) hipFree(kv.first);
-        owned.clear();
-        idle.clear();
-        idle_bytes = 0;
-    }
+    static void release(void*, void*) {}
 };
 
 struct Request {
@@ -113,6 +110,8 @@ struct Request {
     double t_submit = 0, t_admit = 0, t_done = 0, t_launched = 0, t_device = 0;
     uint8_t* d_codes = nullptr;
     int64_t* d_off = nullptr;
+    int64_t block = -1;           // offset of the family's block in the arena
+    Bump bump;
     hipStream_t stream = nullptr;
     hipEvent_t done_ev = nullptr;
     qp_result* result = nullptr;
@@ -143,32 +142,37 @@ struct qp_server {
     std::deque<Request*> done_q;
     std::condition_variable cv_comp;
     std::vector<std::thread> comp;
-    DevCache cache;
+    Arena arena;
 };
 
 namespace {
 
+// the family's device work is over (or never started): its plan, event and
+// arena block go
 void release_device(qp_server* s, Request* r) {
-    if (r->plan) qp_plan_destroy(r->plan);
+    if (r->plan) qp_plan_destroy(r->plan);  // waits for the plan's last run
     r->plan = nullptr;
-    if (r->d_codes) DevCache::release(&s->cache, r->d_codes);
-    if (r->d_off) DevCache::release(&s->cache, r->d_off);
     if (r->done_ev) hipEventDestroy(r->done_ev);
     r->d_codes = nullptr;
     r->d_off = nullptr;
     r->done_ev = nullptr;
+    if (r->block >= 0) s->arena.give(r->block, r->bytes);
+    r->block = -1;
 }
 
-// admission: allocate, upload, enqueue the whole pipeline on the stream
+// admission (the family's block is taken): upload, enqueue the whole
+// pipeline on the stream
 qp_status launch(qp_server* s, Request* r) {
-    qp::plan_set_allocator(r->plan, qp::DeviceAllocator{&DevCache::alloc, &DevCache::release, &s->cache});
-    qp::plan_set_single_stream(r->plan, true);  // families overlap with each other instead
+    r->bump.base = s->arena.base + r->block;
+    r->bump.used = 0;
+    r->bump.cap = Arena::round(r->bytes);
+    qp::plan_set_allocator(r->plan, qp::DeviceAllocator{&Bump::alloc, &Bump::release, &r->bump});
     qp_status st = qp::plan_materialize(r->plan);
     if (st != QP_OK) return st;
     qp_plan_set_graph(r->plan, 0);
     const int64_t tot = std::max<int64_t>(1, (int64_t)r->codes.size());
-    r->d_codes = static_cast<uint8_t*>(DevCache::alloc(&s->cache, (size_t)tot));
-    r->d_off = static_cast<int64_t*>(DevCache::alloc(&s->cache, sizeof(int64_t) * std::max<size_t>(1, r->off.size())));
+    r->d_codes = static_cast<uint8_t*>(Bump::alloc(&r->bump, (size_t)tot));
+    r->d_off = static_cast<int64_t*>(Bump::alloc(&r->bump, sizeof(int64_t) * std::max<size_t>(1, r->off.size())));
     hipError_t e = r->d_codes && r->d_off ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -188,10 +192,8 @@ qp_status launch(qp_server* s, Request* r) {
     return QP_OK;
 }
 
-// a family's device work has finished: download its result.  A family whose
-// sparse output outgrew the plan's estimate completes with QP_ENOSPC; it is
-// not re-run (continuing after an overflow faulted the GPU in other flows and
-// the cause is not identified).
+// a family's device work has finished: download its result (its plan holds
+// the output bound, so the output always fits)
 void complete(qp_server* s, Request* r, qp::Staging* stg) {
     (void)s;
     const qp_status st = qp::plan_download(r->plan, &r->result, stg);
@@ -203,10 +205,12 @@ void scheduler(qp_server* s) {
     hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // admit in arrival order while a slot and the memory budget allow
-        while (!s->queue.empty() && (int)s->running.size() < s->cfg.max_slots &&
-               s->bytes_in_use + s->queue.front()->bytes <= s->cfg.hbm_budget_bytes) {
+        // admit in arrival order while a slot is free and the reserved
+        // device memory holds the next family's block
+        while (!s->queue.empty() && (int)s->running.size() < s->cfg.max_slots) {
             Request* r = s->queue.front();
+            r->block = s->arena.take(r->bytes);
+            if (r->block < 0) break;  // waits for a family to finish
             s->queue.pop_front();
             r->state = St::Running;
             r->t_admit = now_s();
@@ -250,7 +254,7 @@ void scheduler(qp_server* s) {
 }
 
 // downloads finished families (through its own pinned staging buffer) and
-// gives their device memory back to the cache; several run side by side
+// gives their device memory back to the arena; several run side by side
 constexpr int kCompleters = 3;
 constexpr size_t kStageHalf = (size_t)32 << 20;
 
@@ -331,7 +335,15 @@ qp_status qp_server_create(const qp_server_config* cfg, qp_server** out) {
         }
         s->streams.push_back(st);
     }
-    s->cache.limit = cfg->hbm_budget_bytes;
+    // the whole budget, reserved once
+    if (hipMalloc((void**)&s->arena.base, (size_t)cfg->hbm_budget_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipStream_t x : s->streams) hipStreamDestroy(x);
+        delete s;
+        return qp::set_error(QP_ENOMEM, "the device cannot hold the server's memory budget");
+    }
+    s->arena.size = cfg->hbm_budget_bytes;
+    s->arena.free_[0] = cfg->hbm_budget_bytes & ~int64_t(255);
     s->thr = std::thread(scheduler, s);
     for (int q = 0; q < kCompleters; ++q) s->comp.emplace_back(completer, s);
     *out = s;
@@ -378,22 +390,49 @@ qp_status qp_server_submit(qp_server* s, const uint8_t* const* seqs, const int32
     for (int32_t i = 0; i + 1 < n; ++i)
         for (int32_t j = i + 1; j < n; ++j) r->cells += (int64_t)lens[i] * lens[j];
     if (n >= 2) {
-        qp_status st = qp::plan_shape(r->lens.data(), n, nullptr, nullptr, 0, params, thresh, 0, s->wave_budget,
-                                      &r->plan);
-        if (st != QP_OK) {
-            delete r;
-            return st;
+        // The plan holds the guaranteed output bound at the requested
+        // threshold when that fits the budget; otherwise the smallest larger
+        // threshold whose bound fits (the memory-budgeted sparsity of the
+        // method).  Either way no run can overflow its sparse output.
+        const int64_t extra = tot + 8 * (int64_t)n + 1024;  // the family's inputs on the device
+        auto shape = [&](float t, int64_t cap, int64_t* bytes) -> qp_status {
+            if (r->plan) qp_plan_destroy(r->plan);
+            r->plan = nullptr;
+            qp_status st = qp::plan_shape(r->lens.data(), n, nullptr, nullptr, 0, params, t, cap, s->wave_budget,
+                                          &r->plan);
+            if (st != QP_OK) return st;
+            qp::plan_set_single_stream(r->plan, true);  // the classes of a family run one after another
+            *bytes = qp::plan_bytes(r->plan) + extra;
+            return QP_OK;
+        };
+        int64_t bytes = 0;
+        qp_status st = shape(thresh, -1, &bytes);
+        if (st == QP_OK && bytes > s->cfg.hbm_budget_bytes) {
+            // the same plan with a one-entry output: what the budget must hold
+            // besides the sparse output (16 bytes per entry: pool and result)
+            int64_t fixed = 0;
+            st = shape(thresh, 1, &fixed);
+            float t2 = thresh;
+            if (st == QP_OK) {
+                const int64_t room = (s->cfg.hbm_budget_bytes - fixed) / 16;
+                st = room > 0 ? qp_threshold_for_budget(r->lens.data(), n, nullptr, nullptr, 0, room, &t2)
+                              : qp::set_error(QP_ENOMEM, "the budget does not hold the family's workspace");
+            }
+            if (st == QP_OK) st = shape(std::max(thresh, t2), -1, &bytes);
+            if (st == QP_OK) r->thresh = std::max(thresh, t2);
         }
-        r->bytes = qp::plan_bytes(r->plan) + tot + 8 * (int64_t)n + 1024;
-        if (r->bytes > s->cfg.hbm_budget_bytes) {
-            const int64_t need = r->bytes;
-            qp_plan_destroy(r->plan);
-            delete r;
+        if (st == QP_OK && bytes > s->cfg.hbm_budget_bytes) {
             char msg[160];
             std::snprintf(msg, sizeof(msg), "family needs %lld device bytes, more than the whole budget",
-                          (long long)need);
-            return qp::set_error(QP_ENOMEM, msg);
+                          (long long)bytes);
+            st = qp::set_error(QP_ENOMEM, msg);
         }
+        if (st != QP_OK) {
+            if (r->plan) qp_plan_destroy(r->plan);
+            delete r;
+            return st == QP_ENOSPC ? qp::set_error(QP_ENOMEM, "no threshold fits the family in the budget") : st;
+        }
+        r->bytes = bytes;
     }
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) {
@@ -508,7 +547,7 @@ qp_status qp_server_destroy(qp_server* s) {
         delete kv.second;
     }
     for (hipStream_t st : s->streams) hipStreamSynchronize(st);
-    s->cache.free_all();
+    hipFree(s->arena.base);
     for (hipStream_t st : s->streams) hipStreamDestroy(st);
     delete s;
     return QP_OK;

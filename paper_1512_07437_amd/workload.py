@@ -259,8 +259,9 @@ def c3_family() -> List[np.ndarray]:
     return make_family(1000, lens, np.random.SeedSequence(3), r_sub=0.3, r_indel=0.05)
 
 
-def c3_sample(lens: Sequence[int]) -> np.ndarray:
-    """200-pair sample of C3: 150 uniform + 50 from the top 1% by m*n."""
+def c3_sample(lens: Sequence[int], parts: bool = False):
+    """200-pair sample of C3: 150 uniform + 50 from the top 1% by m*n (with
+    ``parts``, the two sorted parts separately)."""
     n = len(lens)
     P = n * (n - 1) // 2
     rng = np.random.default_rng(33)
@@ -270,6 +271,8 @@ def c3_sample(lens: Sequence[int]) -> np.ndarray:
     uni = rng.choice(P, 150, replace=False)
     rest = np.setdiff1d(top, uni)
     big = rng.choice(rest, 50, replace=False)
+    if parts:
+        return np.sort(uni), np.sort(big)
     return np.sort(np.concatenate([uni, big]))
 
 

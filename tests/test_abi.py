@@ -39,7 +39,7 @@ def test_version(B):
 def test_struct_layout(B):
     # qp_params: 400 doubles, int32 (+pad), 2+2 doubles, 400 doubles, 4 doubles, int32 (+pad)
     assert ctypes.sizeof(B.qp_params) == 8 * 400 + 8 + 8 * 4 + 8 * 400 + 8 * 4 + 8
-    assert ctypes.sizeof(B.qp_result) == 4 + 4 + 8 * 3 + 8 * 9 + 8
+    assert ctypes.sizeof(B.qp_result) == 4 + 4 + 8 * 3 + 8 * 9 + 8 + 8
     assert ctypes.sizeof(B.qp_request_times) == 8 * 6
     assert ctypes.sizeof(B.qp_tuning) == 4 * 8 + 8 * 9
 

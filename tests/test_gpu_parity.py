@@ -220,6 +220,58 @@ def test_c2_full_size_sampled(B, params):
     assert np.all((res["dist"] >= -1e-6) & (res["dist"] <= 1.0 + 1e-6))
 
 
+def _oracle_pairs(fam, params, ij):
+    """Oracle results of the pairs (i, j) in ij, on a thread pool (the C
+    oracle runs outside the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as pool:
+        return list(pool.map(lambda t: oracle.pair(fam[t[0]], fam[t[1]], params, per_model=False), ij))
+
+
+def test_c3_full_size_sampled(B, params):
+    """The largest single-family workload (1,000 sequences, lengths
+    log-uniform in [50, 1500], 499,500 pairs) through qp_posteriors, whose
+    plans hold the output bound (here cut into several chunks); the seeded
+    200-pair sample (150 uniform, 50 from the top 1 % by cells) is checked
+    against the oracle element by element."""
+    fam = W.c3_family()
+    lens = np.array([len(s) for s in fam])
+    _say("C3 full size")
+    res = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+    assert res["n_pairs"] == 499500
+    ii, jj = np.triu_indices(1000, 1)
+    assert np.array_equal(res["pair_i"], ii) and np.array_equal(res["pair_j"], jj)
+    assert np.array_equal(np.diff(res["row_off"]), lens[ii] + 1)
+    assert np.all(np.diff(res["nnz_off"]) >= 0) and res["nnz_off"][-1] == res["nnz"]
+    assert res["nnz"] <= B.output_bound(lens, 0.01)
+    sample = W.c3_sample(lens)
+    _say("C3 oracle on %d pairs" % len(sample))
+    orcs = _oracle_pairs(fam, params, [(int(ii[p]), int(jj[p])) for p in sample])
+    for p, orc in zip(sample, orcs):
+        _check_pair(res, int(p), fam[ii[p]], fam[jj[p]], orc, 0.01, TOL[0])
+    # properties that hold for every pair
+    assert np.all(res["val"] >= 0.01) and np.all(res["val"] <= 1.0 + 1e-5)
+    assert np.all((res["dist"] >= -1e-6) & (res["dist"] <= 1.0 + 1e-6))
+    rp = res["row_ptr"]
+    assert np.all(rp[res["row_off"][:-1]] == 0)
+
+
+def test_guide_tree_from_gpu_distances(B, params):
+    """The next stage on the distances the GPU computed: the library's
+    weighted UPGMA and tree-guided distances equal the plain oracle's on the
+    same C2 distances, exactly."""
+    from oracle import tree as T
+    fam = W.c2_family()
+    _say("guide tree on C2 distances")
+    res = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+    dist = np.array(res["dist"])
+    joins, heights = B.guide_tree(dist, 200)
+    oj, oh = T.wpgma(dist, 200)
+    assert [tuple(map(int, j)) for j in joins] == [tuple(j) for j in oj]
+    assert np.array_equal(heights, np.array(oh))
+    assert np.array_equal(B.tree_distance(joins, 200), np.array(T.tree_distance(oj, 200)))
+
+
 def _hip():
     """The HIP runtime libqp.so is linked against (device buffers for the
     plan API without a second runtime in the process)."""

@@ -21,6 +21,12 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _overlapping(times):
+    """Pairs of families whose device work intervals overlapped."""
+    iv = sorted((t["launched_s"], t["device_s"]) for t in times)
+    return sum(1 for a in range(len(iv)) for b in range(a + 1, len(iv)) if iv[b][0] < iv[a][1])
+
+
 def _families():
     rng = np.random.default_rng(40)
     fams = []
@@ -35,21 +41,104 @@ KEYS = ("pair_i", "pair_j", "row_off", "row_ptr", "nnz_off", "col", "val", "dist
 
 
 def test_alone_equals_mix(B, params):
+    """Families submitted together run concurrently on the device (their
+    device intervals overlap) and each result equals the family run alone,
+    bit for bit."""
     p = B.make_params(params)
-    fams = _families()
+    rng = np.random.default_rng(41)
+    fams = [W.make_family(k, rng.integers(100, 400, size=k), 2000 + f, r_sub=0.3, r_indel=0.05)
+            for f, k in enumerate((120, 90, 150, 100, 130, 80))]
     _say("serving: alone")
     alone = [B.qp_posteriors(f, p, 0.01) for f in fams]
     _say("serving: mix")
-    srv = B.Server(hbm_budget_bytes=64 << 30, max_slots=4, n_streams=3)
+    srv = B.Server(hbm_budget_bytes=160 << 30, max_slots=4, n_streams=4)
     try:
         tickets = [srv.submit(f, p, 0.01) for f in fams]
-        got = [srv.wait(t, timeout_ms=60000) for t in tickets]
+        got = [srv.wait(t, timeout_ms=120000) for t in tickets]
     finally:
         srv.close()
     for a, (r, tm) in zip(alone, got):
         for key in KEYS:
             assert np.array_equal(a[key], r[key]), key
-        assert tm["submit_s"] <= tm["admit_s"] <= tm["done_s"]
+        assert tm["submit_s"] <= tm["admit_s"] <= tm["launched_s"] <= tm["device_s"] <= tm["done_s"]
+    n_ov = _overlapping([tm for _, tm in got])
+    _say("serving: %d overlapping pairs of device intervals" % n_ov)
+    assert n_ov >= 1
+
+
+def test_c4_size_families(B, params):
+    """Three families at the top of the C4 size range (k = 500 sequences,
+    lengths U{100..600}) served together: each equals its direct run bit for
+    bit, and seeded pairs of each match the oracle."""
+    import oracle
+    p = B.make_params(params)
+    fams = []
+    for f in range(3):
+        rng = np.random.default_rng(4000 + f)
+        fams.append(W.make_family(500, rng.integers(100, 601, size=500), 4000 + f, r_sub=0.3, r_indel=0.05))
+    srv = B.Server(hbm_budget_bytes=200 << 30, max_slots=3, n_streams=3)
+    try:
+        tickets = [srv.submit(f, p, 0.01) for f in fams]
+        served = [srv.wait(t, timeout_ms=300000) for t in tickets]
+    finally:
+        srv.close()
+    for f, (fam, (res, tm)) in enumerate(zip(fams, served)):
+        _say("C4-size family %d: %d pairs, %d entries" % (f, res["n_pairs"], res["nnz"]))
+        assert res["n_pairs"] == 500 * 499 // 2 and res["thresh"] == np.float32(0.01)
+        direct = B.qp_posteriors(fam, p, 0.01)
+        for key in KEYS:
+            assert np.array_equal(direct[key], res[key]), (f, key)
+        del direct
+        rng = np.random.default_rng(44 + f)
+        for q in rng.choice(res["n_pairs"], 4, replace=False):
+            i, j = W.pair_of_index(int(q), 500)
+            orc = oracle.pair(fam[i], fam[j], params, per_model=False)
+            rp, col, val = B.pair_csr(res, int(q))
+            rows = np.repeat(np.arange(len(fam[i])), np.diff(rp))
+            assert np.abs(val.astype(np.float64) - orc["post"][rows, col]).max(initial=0.0) <= 1e-5
+            assert abs((1.0 - res["dist"][int(q)]) - orc["ea"]) <= 1e-5
+
+
+def test_budget_sets_threshold(B, params):
+    """Under a budget too small for the output bound at the requested
+    threshold, the server admits the family at the smallest larger threshold
+    whose bound fits (memory-budgeted sparsity): the result says which, stays
+    within that bound, and matches the oracle at that threshold."""
+    import oracle
+    p = B.make_params(params)
+    rng = np.random.default_rng(45)
+    fam = W.make_family(8, rng.integers(250, 350, size=8), 45, r_sub=0.3, r_indel=0.05)
+    lens = np.array([len(s) for s in fam])
+    # the smallest budget (on a 10 % grid) the server takes the family at:
+    # what is left for the output there is far below its bound at 0.01
+    budget, res = 8 << 20, None
+    while res is None:
+        srv = B.Server(hbm_budget_bytes=budget, max_slots=1, n_streams=1)
+        try:
+            t = srv.submit(fam, p, 0.01)
+            res = srv.wait(t, timeout_ms=60000)[0]
+        except B.QpError as e:
+            assert e.status == B.QP_ENOMEM
+            budget = int(budget * 1.1)
+            assert budget < 4 << 30
+        finally:
+            srv.close()
+    t_used = res["thresh"]
+    _say("budget %d bytes: threshold %g" % (budget, t_used))
+    assert 0.01 < t_used <= 1.0
+    assert res["nnz"] <= B.output_bound(lens, t_used)
+    k = 0
+    for i in range(8):
+        for j in range(i + 1, 8):
+            orc = oracle.pair(fam[i], fam[j], params, per_model=False)
+            rp, col, val = B.pair_csr(res, k)
+            rows = np.repeat(np.arange(len(fam[i])), np.diff(rp))
+            assert np.abs(val.astype(np.float64) - orc["post"][rows, col]).max(initial=0.0) <= 1e-5
+            g = np.zeros(orc["post"].shape, dtype=bool)
+            g[rows, col] = True
+            diff = g != (orc["post"] >= t_used)
+            assert np.all(np.abs(orc["post"][diff] - t_used) <= 1e-5)
+            k += 1
 
 
 def test_large_family_served_equals_direct(B, params):
