@@ -310,6 +310,59 @@ int64_t qp_plan_device_bytes(const qp_plan* plan);
 void qp_plan_destroy(qp_plan* plan);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free form, for callers that cannot allocate device memory:
+ * code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels and outputs as a plan created with nnz_capacity =
+ * -1 and run once; no device or host allocation is made on success.
+ * ---------------------------------------------------------------------- */
+
+/* Size of the fixed device workspace behind qp_posteriors_noalloc: one
+ * array per device, held from the first call on that device until the
+ * process ends (256 MiB). */
+#define QP_NOALLOC_SCRATCH_BYTES (256 * 1024 * 1024)
+
+/* Caller-owned device outputs (layout as qp_result) and a status word. */
+typedef struct {
+    int32_t* pair_i;        /* [P] P = n(n-1)/2, pairs i < j in row-major order */
+    int32_t* pair_j;        /* [P]                                            */
+    int64_t* row_off;       /* [P + 1]                                        */
+    int32_t* row_ptr;       /* [sum over pairs of lens[i] + 1]                */
+    int64_t* nnz_off;       /* [P + 1]; nnz_off[P] = entries written          */
+    int32_t* col;           /* [capacity]                                     */
+    float* val;             /* [capacity]                                     */
+    int64_t capacity;       /* entries col / val hold: >= qp_output_bound     */
+    double* dist;           /* [P]                                            */
+    double* log_z;          /* [2P]                                           */
+    int32_t* status;        /* [1] written at the end of the run: 0 = OK;
+                               bit 2 (4): a residue code outside the
+                               alphabet; bit 1 (2): a row held more entries
+                               than its slots; bit 0 (1): output overflow
+                               (cannot happen at capacity >= the bound)     */
+} qp_noalloc_out;
+
+/*
+ * All-pairs posteriors of one family with no allocation: every workspace
+ * buffer (tables, aligned sequence copy, pair schedule, output pool, per-wave
+ * scratch) is carved out of the fixed QP_NOALLOC_SCRATCH_BYTES device array.
+ *   d_seqs, d_seq_off  device inputs as for qp_plan_run
+ *   lens[n], params, thresh  host values as for qp_plan_create
+ *   out                caller-owned device outputs, sized as documented
+ *   stream             hipStream_t (NULL = legacy default)
+ * Asynchronous: every step is enqueued on `stream`; the outputs and
+ * out->status are valid once it has been synchronised.  Fewer waves run than
+ * in a plan when the per-wave scratch of the family's longest pairs does not
+ * fit the remaining workspace for a full grid.  QP_ENOMEM (before anything
+ * is enqueued) when the tables, pair lists, an output pool of the bound's
+ * size and one block of waves do not fit the workspace; QP_EINVAL for
+ * invalid inputs or out->capacity below qp_output_bound.  Every call on a
+ * device shares that device's workspace and leaves its contents behind:
+ * calls that overlap on one device (different streams or threads without
+ * ordering) race and must be serialised by the caller.
+ */
+qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t* d_seq_off, const int32_t* lens, int32_t n,
+                                const qp_params* params, float thresh, const qp_noalloc_out* out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Guide tree (the stage after the posteriors; paper: Methods, opening
  * paragraph -- weighted UPGMA on the pairwise distances -- and "Selective
  * consistency" -- the tree-guided distance).  Host memory, host computation.

@@ -61,6 +61,13 @@ class qp_request_times(ctypes.Structure):
                 ("cells", ctypes.c_int64), ("launched_s", ctypes.c_double), ("device_s", ctypes.c_double)]
 
 
+class qp_noalloc_out(ctypes.Structure):
+    _fields_ = [("pair_i", ctypes.c_void_p), ("pair_j", ctypes.c_void_p), ("row_off", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("nnz_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("capacity", ctypes.c_int64), ("dist", ctypes.c_void_p),
+                ("log_z", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
 # every function the header declares: name -> (restype, argtypes)
 _P = ctypes.POINTER
 _u8pp = _P(_P(ctypes.c_uint8))
@@ -111,6 +118,8 @@ SIGNATURES = {
     "qp_guide_tree": (ctypes.c_int, [_P(ctypes.c_double), ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_double)]),
     "qp_tree_distance": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32)]),
     "qp_get_tuning": (ctypes.c_int, [_P(qp_tuning)]),
+    "qp_posteriors_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _P(ctypes.c_int32), ctypes.c_int32,
+                                             _P(qp_params), ctypes.c_float, _P(qp_noalloc_out), ctypes.c_void_p]),
 }
 
 
@@ -431,6 +440,25 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_OUT_FIELDS = ("pair_i", "pair_j", "row_off", "row_ptr", "nnz_off", "col", "val", "dist", "log_z", "status")
+
+
+def posteriors_noalloc(d_seqs_ptr: int, d_off_ptr: int, lens, params: qp_params, thresh: float,
+                       out_ptrs: Dict[str, int], capacity: int, stream_ptr: int):
+    """qp_posteriors_noalloc: enqueue the allocation-free pipeline on a
+    stream.  out_ptrs maps each qp_noalloc_out array name to a device
+    pointer the caller owns (sizes as documented in include/qp.h); capacity
+    is the entries col / val hold."""
+    lens = np.ascontiguousarray(lens, dtype=np.int32)
+    o = qp_noalloc_out()
+    for name in NOALLOC_OUT_FIELDS:
+        setattr(o, name, ctypes.c_void_p(int(out_ptrs[name])))
+    o.capacity = int(capacity)
+    _check(lib.qp_posteriors_noalloc(ctypes.c_void_p(d_seqs_ptr), ctypes.c_void_p(d_off_ptr),
+                                     lens.ctypes.data_as(_P(ctypes.c_int32)), len(lens), ctypes.byref(params),
+                                     ctypes.c_float(thresh), ctypes.byref(o), ctypes.c_void_p(stream_ptr)))
 
 
 def device_inputs(seqs: Sequence[np.ndarray], device: str = "cuda:0"):

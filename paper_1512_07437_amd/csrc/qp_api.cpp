@@ -265,26 +265,48 @@ qp_status validate_lens(const int32_t* lens, int32_t n) {
 
 // sizes of one per-wave scratch slot of a kernel class
 void size_slot(const qp_plan* pl, qp_plan::ClassPlan* c) {
-    qp::PairArgs& a = c->args;
-    const int64_t v2 = pl->fp64 ? 16 : 8;
-    const int64_t steps = (int64_t)c->nmax + qp::kWave - 1;
-    a.spill_band_stride = steps * qp::kWave * c->R;
-    a.exps_band_stride = ((steps + qp::kRescaleEvery - 1) / qp::kRescaleEvery) * qp::kWave;
-    a.bnd_stride = c->nmax + 2;
-    int64_t off = align256(c->nb_max * a.spill_band_stride * v2);
-    a.off_exps = off;
-    off += align256(c->nb_max * a.exps_band_stride * 8);
-    a.off_fb = off;
-    off += align256(2 * a.bnd_stride * (int64_t)qp::fwd_bnd_bytes(pl->fp64));
-    a.off_bb = off;
-    off += align256(2 * a.bnd_stride * (int64_t)qp::bwd_bnd_bytes(pl->fp64));
-    // hit log: at most cap records of 16 bytes per row
-    a.off_log = off;
-    off += align256((int64_t)c->mmax * c->cap * 16);
-    a.slot_bytes = off;
+    qp::slot_layout(c->R, c->mmax, c->nmax, c->nb_max, c->cap, pl->fp64, &c->args);
 }
 
 }  // namespace
+
+// ------------------------------------------- helpers shared with qp_noalloc
+int qp::alphabet_of(const qp_params* p) { return ::alphabet_of(p); }
+int64_t qp::row_bound(int32_t cols, float thresh) { return ::row_bound(cols, thresh); }
+qp_status qp::validate_lens(const int32_t* lens, int32_t n) { return ::validate_lens(lens, n); }
+qp_status qp::check_device(int* dev, int* n_cu) { return ::check_device(dev, n_cu); }
+qp_status qp::fail_msg(qp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+void qp::current_tuning(qp::ClassMap* map, double* waves_frac) {
+    std::lock_guard<std::mutex> g(g_tuning_mu);
+    for (int r = 0; r < qp::kRMax; ++r) map->c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
+    for (int c = 0; c < qp::kClasses; ++c) waves_frac[c] = g_tuning.waves_frac[c];
+}
+void qp::slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, qp::PairArgs* a) {
+    const int64_t v2 = fp64 ? 16 : 8;
+    const int64_t steps = (int64_t)nmax + qp::kWave - 1;
+    a->spill_band_stride = steps * qp::kWave * R;
+    a->exps_band_stride = ((steps + qp::kRescaleEvery - 1) / qp::kRescaleEvery) * qp::kWave;
+    a->bnd_stride = nmax + 2;
+    int64_t off = align256(nb_max * a->spill_band_stride * v2);
+    a->off_exps = off;
+    off += align256(nb_max * a->exps_band_stride * 8);
+    a->off_fb = off;
+    off += align256(2 * a->bnd_stride * (int64_t)qp::fwd_bnd_bytes(fp64));
+    a->off_bb = off;
+    off += align256(2 * a->bnd_stride * (int64_t)qp::bwd_bnd_bytes(fp64));
+    // hit log: at most cap records of 16 bytes per row
+    a->off_log = off;
+    off += align256((int64_t)mmax * cap * 16);
+    a->slot_bytes = off;
+}
 
 // per-class launch arguments: the shared fields plus the class's scratch
 static void set_class_args(qp_plan* pl) {

@@ -160,5 +160,17 @@ qp_result* result_alloc(int32_t n_seqs, int64_t P, int64_t rows, int64_t nnz);
 bool result_pinned(const qp_result* r);
 qp_status plan_materialize(qp_plan* pl);
 qp_status set_error(qp_status st, const char* msg);
+// formatted error message for qp_last_error; returns st
+qp_status fail_msg(qp_status st, const char* fmt, ...);
+
+// host helpers shared by the entry points (qp_api.cpp)
+int alphabet_of(const qp_params* p);               // residue codes 0..alphabet-1
+int64_t row_bound(int32_t cols, float thresh);     // slots of one output row
+qp_status validate_lens(const int32_t* lens, int32_t n);
+qp_status check_device(int* dev, int* n_cu);       // current device is gfx950
+void current_tuning(ClassMap* map, double* waves_frac);  // the tuning table in force
+// layout of one per-wave scratch slot of a kernel class with R rows per lane,
+// at most mmax rows, nmax columns and nb_max bands, cap output slots per row
+void slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, PairArgs* a);
 
 }  // namespace qp

@@ -42,6 +42,8 @@ def test_struct_layout(B):
     assert ctypes.sizeof(B.qp_result) == 4 + 4 + 8 * 3 + 8 * 9 + 8 + 8
     assert ctypes.sizeof(B.qp_request_times) == 8 * 6
     assert ctypes.sizeof(B.qp_tuning) == 4 * 8 + 8 * 9
+    assert ctypes.sizeof(B.qp_noalloc_out) == 8 * 11
+    assert [f[0] for f in B.qp_noalloc_out._fields_ if f[0] != "capacity"] == list(B.NOALLOC_OUT_FIELDS)
 
 
 def _good(params):
@@ -179,3 +181,29 @@ def test_tuning_file_is_valid(B):
     t.waves_frac[:] = d["waves_frac"]
     assert B.lib.qp_set_tuning(ctypes.byref(t)) == 0
     assert B.get_tuning()["rows_per_lane"] == d["rows_per_lane"]
+
+
+def test_noalloc_validation_before_device(B, params):
+    """The allocation-free entry point checks its inputs, and that the
+    caller's output capacity covers the output bound, before any device call."""
+    p = _good(params)
+    lens = [50, 60, 70]
+    ptrs = {k: 4096 for k in B.NOALLOC_OUT_FIELDS}
+    bound = B.output_bound(lens, 0.01)
+    with pytest.raises(B.QpError) as e:
+        B.posteriors_noalloc(4096, 4096, lens, p, 0.01, ptrs, bound - 1, 0)
+    assert e.value.status == B.QP_EINVAL and "output bound" in str(e.value)
+    with pytest.raises(B.QpError) as e:
+        B.posteriors_noalloc(4096, 4096, [50, 0], p, 0.01, ptrs, bound, 0)
+    assert e.value.status == B.QP_EINVAL
+    with pytest.raises(B.QpError) as e:
+        B.posteriors_noalloc(4096, 4096, lens, p, 1.5, ptrs, bound, 0)
+    assert e.value.status == B.QP_EINVAL
+    missing = dict(ptrs, col=0)
+    with pytest.raises(B.QpError) as e:
+        B.posteriors_noalloc(4096, 4096, lens, p, 0.01, missing, bound, 0)
+    assert e.value.status == B.QP_EINVAL
+    if _hip_devices() == 0:
+        with pytest.raises(B.QpError) as e:
+            B.posteriors_noalloc(4096, 4096, lens, p, 0.01, ptrs, bound, 0)
+        assert e.value.status == B.QP_EDEVICE
