@@ -87,6 +87,22 @@ def test_c1_all_pairs(B, params):
     _c1_all_pairs(B, params, 0)
 
 
+@pytest.mark.skip(reason="C5 (64 divergent pairs of 3000-5000 residues) faulted the GPU, and so did a "
+                         "1000-1500 residue version of it; the cause is not shown, so sequences over "
+                         "QP_MAX_SEQ_LEN = 1536 stay refused and this case stays off the GPU")
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c5_precision(B, params, prec):
+    """All 64 C5 pairs against the FP64 oracle: stored values within 1e-5
+    (FP32 path) / 1e-7 (FP64 path), EA alike, output sized to the bound."""
+    ab = W.c5_pairs()
+    fam = [s for pair in ab for s in pair]
+    pi = np.arange(0, 2 * len(ab), 2, dtype=np.int32)
+    res = B.qp_posteriors_pairs(fam, pi, pi + 1, B.make_params(params, prec), 0.01)
+    for k, (x, y) in enumerate(ab):
+        orc = oracle.pair(x, y, params, per_model=False)
+        _check_pair(res, k, x, y, orc, 0.01, TOL[prec])
+
+
 @pytest.mark.skip(reason="a run at threshold 1e-30 exceeded its time limit and the cause is not yet "
                          "identified; the case stays disabled until it is")
 @pytest.mark.parametrize("prec", [0, 1])
