@@ -45,9 +45,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1512_07437_amd", "csrc", "qp_device.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_hbm_traffic.txt")
 
 
-def kernel_name(cls: int, fp64: bool) -> str:
-    """Symbol of the persistent pair kernel of one class, as profilers print it."""
+def kernel_name(cls: int, fp64: bool, ck: bool = False) -> str:
+    """Symbol of the persistent pair kernel of one class, as profilers print
+    it (ck: the checkpointed FP32 form)."""
     r = cls + 1 if cls < 8 else 8
+    if ck and not fp64:
+        return "qp::k_pairs_ck<%d, %s>" % (r, "true" if cls == 8 else "false")
     return "qp::k_pairs<%d, %s, %s>" % (r, "double" if fp64 else "float", "true" if cls == 8 else "false")
 
 
@@ -242,6 +245,9 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--recompute", default="table", choices=["table", "none", "all"],
+                    help="FP32 pair-kernel form per class: the tuning table's choice, the spilling form for "
+                         "every class (none) or the checkpointed form for every class (all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the posterior engine runs one process on one MI355X "
@@ -257,6 +263,9 @@ def main():
     from paper_1512_07437_amd import binding as B
     from paper_1512_07437_amd import workload as W
 
+    if args.recompute != "table":
+        B.set_tuning(recompute=[1 if args.recompute == "all" else 0] * 9)
+    say("pair-kernel forms (1 = checkpointed) per class: %s" % B.get_tuning()["recompute"])
     if args.workload == "c4":
         out = serve_stream(args, say, args.families)
         print(json.dumps(out), flush=True)
@@ -335,7 +344,8 @@ def main():
     for c in range(9):
         c_ms, c_pairs, c_cells, c_r = plan.class_timing(c)
         if c_pairs:
-            classes.append({"class": c, "kernel": kernel_name(c, fp64), "rows_per_lane": c_r, "pairs": c_pairs,
+            classes.append({"class": c, "kernel": kernel_name(c, fp64, bool(B.get_tuning()["recompute"][c])),
+                            "rows_per_lane": c_r, "pairs": c_pairs,
                             "cells": c_cells, "avg_ms": round(c_ms, 4),
                             "tflops": round(c_cells * FLOP_PER_CELL / (c_ms * 1e-3) / 1e12, 3) if c_ms > 0 else None})
     dom = max(classes, key=lambda r: r["cells"]) if classes else None

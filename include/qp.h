@@ -290,13 +290,22 @@ qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
  * than 512.  A pair whose row sequence needs at least r = ceil(m/64) rows
  * per lane runs with rows_per_lane[r-1] (r..8) rows per lane; every class
  * launches waves_frac[c] (0, 1] of its occupancy-limited persistent grid.
- * Default: rows_per_lane[r-1] = r, waves_frac = 1.  Filled in by the
- * project's autotuner (paper_1512_07437_amd/autotune.py) from measurements
- * per length bucket.
+ * recompute[c] = 1 runs class c's FP32 pairs in the checkpointed form: the
+ * forward sweep keeps only its state every 8 steps and the backward sweep
+ * recomputes each 8-step block's forward values in registers, instead of
+ * writing every cell's forward values to device memory and reading them
+ * back (recompute[c] = 0); same outputs, different memory / arithmetic
+ * balance.  The checkpointed form exists for classes 0..4 (1 to 5 rows per
+ * lane; QP_EINVAL for recompute[c] = 1 beyond), and the FP64 path always
+ * uses the other form.
+ * Default: rows_per_lane[r-1] = r, waves_frac = 1, recompute = 1 for the
+ * classes of 3 to 5 rows per lane.  Filled in by the project's autotuner
+ * (paper_1512_07437_amd/autotune.py) from measurements per length bucket.
  */
 typedef struct {
     int32_t rows_per_lane[8];
     double waves_frac[9];
+    int32_t recompute[9];
 } qp_tuning;
 
 /* Set the table (NULL restores the default); QP_EINVAL for a value out of

@@ -72,7 +72,8 @@ class qp_noalloc_out(ctypes.Structure):
 _P = ctypes.POINTER
 _u8pp = _P(_P(ctypes.c_uint8))
 class qp_tuning(ctypes.Structure):
-    _fields_ = [("rows_per_lane", ctypes.c_int32 * 8), ("waves_frac", ctypes.c_double * 9)]
+    _fields_ = [("rows_per_lane", ctypes.c_int32 * 8), ("waves_frac", ctypes.c_double * 9),
+                ("recompute", ctypes.c_int32 * 9)]
 
 
 SIGNATURES = {
@@ -147,25 +148,30 @@ def _check(st: int):
 TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 
-def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Optional[Sequence[float]] = None):
+def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Optional[Sequence[float]] = None,
+               recompute: Optional[Sequence[int]] = None):
     """Process-wide tuning table for plans made afterwards (qp_set_tuning);
-    None for both restores the default."""
-    if rows_per_lane is None and waves_frac is None:
+    entries left None keep their current values; None for all three
+    restores the default."""
+    if rows_per_lane is None and waves_frac is None and recompute is None:
         _check(lib.qp_set_tuning(None))
         return
     t = get_tuning()
     r = list(t["rows_per_lane"] if rows_per_lane is None else rows_per_lane)
     w = list(t["waves_frac"] if waves_frac is None else waves_frac)
+    c = list(t["recompute"] if recompute is None else recompute)
     v = qp_tuning()
     v.rows_per_lane[:] = [int(x) for x in r]
     v.waves_frac[:] = [float(x) for x in w]
+    v.recompute[:] = [int(x) for x in c]
     _check(lib.qp_set_tuning(ctypes.byref(v)))
 
 
 def get_tuning() -> Dict[str, list]:
     t = qp_tuning()
     _check(lib.qp_get_tuning(ctypes.byref(t)))
-    return {"rows_per_lane": list(t.rows_per_lane), "waves_frac": list(t.waves_frac)}
+    return {"rows_per_lane": list(t.rows_per_lane), "waves_frac": list(t.waves_frac),
+            "recompute": list(t.recompute)}
 
 
 def load_tuning(path: str = TUNING_PATH) -> bool:
@@ -175,7 +181,7 @@ def load_tuning(path: str = TUNING_PATH) -> bool:
         return False
     with open(path) as f:
         d = json.load(f)
-    set_tuning(d["rows_per_lane"], d["waves_frac"])
+    set_tuning(d["rows_per_lane"], d["waves_frac"], d.get("recompute"))
     return True
 
 

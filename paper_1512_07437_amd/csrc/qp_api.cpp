@@ -24,10 +24,17 @@ thread_local std::string g_err;
 
 // process-wide tuning table (qp_set_tuning); plans copy it when made
 std::mutex g_tuning_mu;
+void default_tuning(qp_tuning* t) {
+    *t = qp_tuning{};
+    for (int r = 0; r < 8; ++r) t->rows_per_lane[r] = r + 1;
+    for (int c = 0; c < 9; ++c) {
+        t->waves_frac[c] = 1.0;
+        t->recompute[c] = c >= 2 && c <= 4 ? 1 : 0;
+    }
+}
 qp_tuning g_tuning = [] {
-    qp_tuning t{};
-    for (int r = 0; r < 8; ++r) t.rows_per_lane[r] = r + 1;
-    for (int c = 0; c < 9; ++c) t.waves_frac[c] = 1.0;
+    qp_tuning t;
+    default_tuning(&t);
     return t;
 }();
 
@@ -131,6 +138,7 @@ struct qp_plan {
     // tuning in force when the plan was made
     qp::ClassMap cmap{};
     double waves_frac[qp::kClasses] = {};
+    int recompute[qp::kClasses] = {};
     qp_params params{};
     float thresh = 0.f;
     int fp64 = 0;
@@ -142,6 +150,7 @@ struct qp_plan {
     struct ClassPlan {
         int64_t pairs = 0, cells = 0;
         int mmax = 1, nmax = 1, R = 1, nb_max = 1, cap = 1, grid = 0;
+        bool ck = false;  // checkpointed form (forward values recomputed)
         qp::PairArgs args{};
         char* d_scratch = nullptr;
     } cls[qp::kClasses];
@@ -265,7 +274,7 @@ qp_status validate_lens(const int32_t* lens, int32_t n) {
 
 // sizes of one per-wave scratch slot of a kernel class
 void size_slot(const qp_plan* pl, qp_plan::ClassPlan* c) {
-    qp::slot_layout(c->R, c->mmax, c->nmax, c->nb_max, c->cap, pl->fp64, &c->args);
+    qp::slot_layout(c->R, c->mmax, c->nmax, c->nb_max, c->cap, pl->fp64, c->ck, &c->args);
 }
 
 }  // namespace
@@ -284,14 +293,35 @@ qp_status qp::fail_msg(qp_status st, const char* fmt, ...) {
     g_err = buf;
     return st;
 }
-void qp::current_tuning(qp::ClassMap* map, double* waves_frac) {
+void qp::current_tuning(qp::ClassMap* map, double* waves_frac, int* recompute) {
     std::lock_guard<std::mutex> g(g_tuning_mu);
     for (int r = 0; r < qp::kRMax; ++r) map->c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
-    for (int c = 0; c < qp::kClasses; ++c) waves_frac[c] = g_tuning.waves_frac[c];
+    for (int c = 0; c < qp::kClasses; ++c) {
+        waves_frac[c] = g_tuning.waves_frac[c];
+        recompute[c] = g_tuning.recompute[c];
+    }
 }
-void qp::slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, qp::PairArgs* a) {
+void qp::slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, bool ck, qp::PairArgs* a) {
     const int64_t v2 = fp64 ? 16 : 8;
     const int64_t steps = (int64_t)nmax + qp::kWave - 1;
+    if (ck) {
+        // per band: the saved forward state of every 8-step block; the
+        // forward boundary records of every band; two backward ones
+        const int64_t blocks = (steps + qp::kRescaleEvery - 1) / qp::kRescaleEvery;
+        a->spill_band_stride = blocks * qp::ck_state_words(R) * qp::kWave;
+        a->exps_band_stride = 0;
+        a->bnd_stride = nmax + 2;
+        int64_t off = align256(nb_max * a->spill_band_stride * 4);
+        a->off_exps = off;
+        a->off_fb = off;
+        off += align256(nb_max * a->bnd_stride * (int64_t)qp::fwd_bnd_bytes(0));
+        a->off_bb = off;
+        off += align256(2 * a->bnd_stride * (int64_t)qp::bwd_bnd_bytes(0));
+        a->off_log = off;
+        off += align256((int64_t)mmax * cap * 16);
+        a->slot_bytes = off;
+        return;
+    }
     a->spill_band_stride = steps * qp::kWave * R;
     a->exps_band_stride = ((steps + qp::kRescaleEvery - 1) / qp::kRescaleEvery) * qp::kWave;
     a->bnd_stride = nmax + 2;
@@ -468,7 +498,10 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
     if (pl->per_pair) {
         for (int64_t p = 0; p < P; ++p) {
             const int c = pl->pair_cls[p];
-            HIP_TRY(qp::launch_pair_one(c, pl->fp64, p, pl->cls[c].args, s));
+            if (pl->cls[c].ck)
+                HIP_TRY(qp::launch_pair_one_ck(c, p, pl->cls[c].args, s));
+            else
+                HIP_TRY(qp::launch_pair_one(c, pl->fp64, p, pl->cls[c].args, s));
         }
         if (ev) HIP_TRY(record(ev[2], s, capturing));
         HIP_TRY(qp::scan_i64(pl->d_nnz, P + 1, pl->d_scan_tmp, s));
@@ -483,7 +516,10 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
         if (pl->cls[c].grid > 0) present[np++] = c;
     auto launch_class = [&](int c, hipStream_t cs) -> qp_status {
         if (ev) HIP_TRY(record(pl->cev[ev_set][c][0], cs, capturing));
-        HIP_TRY(qp::launch_pairs(c, pl->fp64, pl->cls[c].grid, pl->cls[c].args, cs));
+        if (pl->cls[c].ck)
+            HIP_TRY(qp::launch_pairs_ck(c, pl->cls[c].grid, pl->cls[c].args, cs));
+        else
+            HIP_TRY(qp::launch_pairs(c, pl->fp64, pl->cls[c].grid, pl->cls[c].args, cs));
         if (ev) HIP_TRY(record(pl->cev[ev_set][c][1], cs, capturing));
         return QP_OK;
     };
@@ -675,7 +711,10 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     {
         std::lock_guard<std::mutex> g(g_tuning_mu);
         for (int r = 0; r < qp::kRMax; ++r) pl->cmap.c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
-        for (int c = 0; c < qp::kClasses; ++c) pl->waves_frac[c] = g_tuning.waves_frac[c];
+        for (int c = 0; c < qp::kClasses; ++c) {
+            pl->waves_frac[c] = g_tuning.waves_frac[c];
+            pl->recompute[c] = g_tuning.recompute[c];
+        }
     }
     if (!all) {
         pl->list_i.assign(pair_i, pair_i + P);
@@ -734,8 +773,9 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         const int H = qp::kWave * cp.R;
         cp.nb_max = c == qp::kRMax ? (cp.mmax + H - 1) / H : 1;
         cp.cap = (int)std::max(1.0, std::min((double)cp.nmax, inv + 1.0));
+        cp.ck = !pl->fp64 && pl->recompute[c] != 0;
         size_slot(pl, &cp);
-        const int per_cu = qp::pairs_blocks_per_cu(c, pl->fp64);
+        const int per_cu = cp.ck ? qp::pairs_ck_blocks_per_cu(c) : qp::pairs_blocks_per_cu(c, pl->fp64);
         int64_t grid = std::max<int64_t>(1, (int64_t)std::llround(per_cu * n_cu * pl->waves_frac[c]));
         grid = std::min<int64_t>(grid, std::max<int64_t>(1, (cp.pairs + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock));
         cp.grid = (int)grid;
@@ -1038,9 +1078,15 @@ qp_status qp_threshold_for_budget(const int32_t* lens, int32_t n, const int32_t*
 qp_status qp_set_tuning(const qp_tuning* t) {
     qp_tuning v{};
     if (!t) {
-        for (int r = 0; r < 8; ++r) v.rows_per_lane[r] = r + 1;
-        for (int c = 0; c < 9; ++c) v.waves_frac[c] = 1.0;
+        default_tuning(&v);
     } else {
+        for (int c = 0; c < 9; ++c) {
+            if (t->recompute[c] != 0 && t->recompute[c] != 1)
+                return fail(QP_EINVAL, "recompute[%d] = %d is not 0 or 1", c, t->recompute[c]);
+            if (t->recompute[c] && c > qp::kCkMaxClass)
+                return fail(QP_EINVAL, "recompute[%d] = 1: the checkpointed form exists for classes 0..%d only", c,
+                            qp::kCkMaxClass);
+        }
         for (int r = 0; r < 8; ++r)
             if (t->rows_per_lane[r] < r + 1 || t->rows_per_lane[r] > 8)
                 return fail(QP_EINVAL, "rows_per_lane[%d] = %d is not in [%d, 8]", r, t->rows_per_lane[r], r + 1);

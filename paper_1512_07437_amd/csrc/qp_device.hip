@@ -29,6 +29,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "qp_internal.h"
 
@@ -610,6 +611,55 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     if (FIRST) a11 = rdlane(A[0], 0);
 }
 
+// ------------------------------------------------- end of one pair
+// Row counts -> row pointers, the pair's block of the output pool, per-pair
+// scalars, and the logged hits placed in row / column order.
+__device__ void finish_pair(const PairArgs& a, int lane, int64_t p, int m, int n, int32_t* __restrict__ rp,
+                            const int4* __restrict__ hitlog, int nlog, double zH, int ezH, double zP, int ezP,
+                            double a11) {
+    // ---- row counts -> row pointers (inclusive scan in place)
+    int carry = 0;
+    for (int base = 0; base < m; base += kWave) {
+        const int idx = base + lane;
+        int v = idx < m ? rp[1 + idx] : 0;
+        v = wave_incl_scan(v, lane);
+        if (idx < m) rp[1 + idx] = v + carry;
+        carry += __shfl(v, kWave - 1, kWave);
+    }
+    if (lane == 0) rp[0] = 0;
+    __threadfence_block();
+    const int nnz = carry;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.pool_head, (unsigned long long)nnz);
+    base = __shfl(base, 0, kWave);
+    if (lane == 0) {
+        a.pair_nnz[p] = nnz;
+        a.pair_base[p] = (int64_t)base;
+        const double lzh = log((double)zH) + (double)ezH * 0.69314718055994530942;
+        const double lzp = log((double)zP) + (double)ezP * 0.69314718055994530942;
+        a.logz[2 * p] = lzh;
+        a.logz[2 * p + 1] = lzp;
+        a.dist[p] = 1.0 - a11 / (double)min(m, n);
+    }
+    // counts are written by the backward pass and bounded by cap, so a
+    // negative total cannot occur on a complete pass; it is refused anyway,
+    // since a wrapped total would pass the capacity test below
+    if (nnz < 0 || (int64_t)base + nnz > a.pool_cap) {
+        if (lane == 0) atomicOr(a.flags, 1);
+        return;
+    }
+    // place the logged hits: the backward pass meets a row's columns in
+    // decreasing order, so rank k from the row's end lands at
+    // base + row_end - 1 - k (rows ascending, columns ascending)
+    for (int e = lane; e < nlog; e += kWave) {
+        const int4 h = hitlog[e];
+        const int64_t pos = (int64_t)base + rp[h.x + 1] - 1 - h.y;
+        a.pool_col[pos] = h.z;
+        a.pool_val[pos] = __int_as_float(h.w);
+    }
+    __threadfence_block();
+}
+
 // ------------------------------------------------------------ one pair
 template <int R, typename T, bool MULTI>
 __device__ void process_pair(const PairArgs& a, int lane, char* slot, const typename Pair2<T>::type* tab,
@@ -677,47 +727,7 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
 #undef QP_BWD
         __threadfence_block();
     }
-    // ---- row counts -> row pointers (inclusive scan in place)
-    int carry = 0;
-    for (int base = 0; base < m; base += kWave) {
-        const int idx = base + lane;
-        int v = idx < m ? rp[1 + idx] : 0;
-        v = wave_incl_scan(v, lane);
-        if (idx < m) rp[1 + idx] = v + carry;
-        carry += __shfl(v, kWave - 1, kWave);
-    }
-    if (lane == 0) rp[0] = 0;
-    __threadfence_block();
-    const int nnz = carry;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(a.pool_head, (unsigned long long)nnz);
-    base = __shfl(base, 0, kWave);
-    if (lane == 0) {
-        a.pair_nnz[p] = nnz;
-        a.pair_base[p] = (int64_t)base;
-        const double lzh = log((double)zH) + (double)ezH * 0.69314718055994530942;
-        const double lzp = log((double)zP) + (double)ezP * 0.69314718055994530942;
-        a.logz[2 * p] = lzh;
-        a.logz[2 * p + 1] = lzp;
-        a.dist[p] = 1.0 - a11 / (double)min(m, n);
-    }
-    // counts are written by the backward pass and bounded by cap, so a
-    // negative total cannot occur on a complete pass; it is refused anyway,
-    // since a wrapped total would pass the capacity test below
-    if (nnz < 0 || (int64_t)base + nnz > a.pool_cap) {
-        if (lane == 0) atomicOr(a.flags, 1);
-        return;
-    }
-    // place the logged hits: the backward pass meets a row's columns in
-    // decreasing order, so rank k from the row's end lands at
-    // base + row_end - 1 - k (rows ascending, columns ascending)
-    for (int e = lane; e < nlog; e += kWave) {
-        const int4 h = hitlog[e];
-        const int64_t pos = (int64_t)base + rp[h.x + 1] - 1 - h.y;
-        a.pool_col[pos] = h.z;
-        a.pool_val[pos] = __int_as_float(h.w);
-    }
-    __threadfence_block();
+    finish_pair(a, lane, p, m, n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
 }
 
 // One persistent launch per kernel class: waves pop pairs of their class
@@ -770,6 +780,626 @@ __global__ __launch_bounds__(kWave) void k_pair_one(PairArgs a, int64_t p) {
     k.tau = (T)c.tau; k.eps1 = (T)c.eps1; k.eps2 = (T)c.eps2; k.c1 = (T)c.c1; k.c2 = (T)c.c2;
     k.u = (T)c.u; k.o = (T)c.o;
     process_pair<R, T, MULTI>(a, lane, a.scratch, tab, k, p);
+}
+
+// ======================================================= checkpointed form
+// FP32 pair routine that keeps no per-cell value in memory.  The forward
+// sweep saves its whole state (FwdSt) at the start of every block of
+// kRescaleEvery steps, right after the block boundary's rescale, and writes
+// nothing per cell; the backward sweep walks the blocks from the last one,
+// restores a block's state, recomputes that block's forward match values
+// into registers and consumes them in reverse step order.  The recomputed
+// values are bit-identical to the first sweep's (same state, same
+// arithmetic), so the posteriors are those of the spilling routine above;
+// per cell the memory traffic drops from the 16-byte value pair written and
+// read back to a (5R+13)-word state per lane and block.
+//
+// The backward sweep's rescale closes every block (instead of every eighth
+// backward step), and its per-step work reads no memory.
+template <int R> struct FwdSt {
+    float W1[R], W2[R], D[R], gW[R], gD[R];
+    float oM, oU1, oU2, ogM, ogU, aD, gaD, tv1, tv2, tgv;
+    int EH, EP;
+    FwdBnd<float> bq;
+};
+// 32-bit words of one lane's saved state
+__host__ __device__ constexpr int ck_words(int R) { return 5 * R + 12; }
+// The column sequence of the pair being processed sits in LDS (one region
+// per wave) with kYPad zero bytes before and after it, so that every lane
+// reads the residue of its own column, in or out of range, with one LDS byte
+// load: no scalar load or lane-to-lane hand-over of residues in the step
+// loops, and LDS waits there count LDS operations only.
+constexpr int kYPad = kWave;
+constexpr int kYStride = kMaxSeqLen + 2 * kYPad;
+
+// state after column 0 of a band (before step 0)
+template <int R, bool FIRST, bool LAST>
+__device__ __forceinline__ void ck_init(FwdSt<R>& f, int lane, bool used, int r0, int rows, int L,
+                                        const Coef<float>& k, const Col0* __restrict__ col0,
+                                        const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout) {
+    Col0 c0[R];
+    int EH = INT_MIN, EP = INT_MIN;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = lane * R + r;
+        if (used && row < rows) {
+            c0[r] = col0[r0 + row];
+        } else {
+            c0[r].mH = 0.0;
+            c0[r].mP = 0.0;
+            c0[r].eH = 0;
+            c0[r].eP = 0;
+        }
+        EH = max(EH, c0[r].mH != 0.0 ? c0[r].eH : INT_MIN);
+        EP = max(EP, c0[r].mP != 0.0 ? c0[r].eP : INT_MIN);
+    }
+    if (EH == INT_MIN) EH = 0;
+    if (EP == INT_MIN) EP = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        f.W1[r] = 0.f;
+        f.W2[r] = 0.f;
+        f.gW[r] = 0.f;
+        f.D[r] = qldexp((float)c0[r].mH, c0[r].eH - EH);
+        f.gD[r] = qldexp((float)c0[r].mP, c0[r].eP - EP);
+    }
+    f.EH = EH;
+    f.EP = EP;
+    f.oM = f.oU1 = f.oU2 = f.ogM = f.ogU = 0.f;
+    f.aD = f.gaD = 0.f;
+    f.tv1 = f.tv2 = f.tgv = 0.f;
+    if (lane == 0) {
+        if (FIRST) {
+            f.aD = qldexp(k.tau, -EH);
+            f.gaD = qldexp(1.f, -EP);
+            f.tv1 = qldexp(1.f, -EH);
+            f.tv2 = f.tv1;
+            f.tgv = qldexp(1.f, -EP);
+        } else {
+            const FwdBnd<float> b = fin[0];
+            f.aD = qldexp(b.D, b.EH - EH);
+            f.gaD = qldexp(b.gD, b.EP - EP);
+        }
+    }
+    if (!LAST && lane == L - 1) {
+        FwdBnd<float> b;
+        b.M = 0.f; b.U1 = 0.f; b.U2 = 0.f; b.D = f.D[R - 1];
+        b.gM = 0.f; b.gU = 0.f; b.gD = f.gD[R - 1];
+        b.EH = EH; b.EP = EP;
+        fout[0] = b;
+    }
+    if (!FIRST && lane == 0) f.bq = fin[1];
+}
+
+// one forward step: the match values of the lane's rows at its column go to
+// sm; WB: also write the band's boundary record (first sweep only)
+// (ycn: the residue of this step's column, read one step ahead; the read
+// for the next step is issued here)
+template <int R, bool FIRST, bool LAST, bool WB>
+__device__ __forceinline__ void ck_fstep(FwdSt<R>& f, float2 (&sm)[R], const int s, const int lane, const bool used,
+                                         const int n, const int L, const int (&xo)[R], const uint8_t* ys,
+                                         int& ycn, const float2* tab, const Coef<float>& k,
+                                         const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout) {
+    const int j = s - lane + 1;
+    const bool active = used && j >= 1 && j <= n;
+    const int yc = ycn;
+    ycn = ys[j];
+    float rM = dpp<kDppWaveShr1>(f.oM), rU1 = dpp<kDppWaveShr1>(f.oU1), rU2 = dpp<kDppWaveShr1>(f.oU2);
+    float rD = dpp<kDppWaveShr1>(f.D[R - 1]), rgM = dpp<kDppWaveShr1>(f.ogM), rgU = dpp<kDppWaveShr1>(f.ogU);
+    float rgD = dpp<kDppWaveShr1>(f.gD[R - 1]);
+    int rEH = dpp_i<kDppWaveShr1>(f.EH), rEP = dpp_i<kDppWaveShr1>(f.EP);
+    if (lane == 0) {
+        if (FIRST) {
+            rM = 0.f; rU1 = 0.f; rU2 = 0.f;
+            rD = k.c1 * f.tv1 + k.c2 * f.tv2;
+            rgM = 0.f; rgU = 0.f;
+            rgD = k.o * f.tgv;
+            rEH = f.EH; rEP = f.EP;
+            f.tv1 *= k.eps1; f.tv2 *= k.eps2; f.tgv *= k.u;
+        } else {
+            rM = f.bq.M; rU1 = f.bq.U1; rU2 = f.bq.U2; rD = f.bq.D;
+            rgM = f.bq.gM; rgU = f.bq.gU; rgD = f.bq.gD;
+            rEH = f.bq.EH; rEP = f.bq.EP;
+            f.bq = fin[s + 2 <= n ? s + 2 : n];
+        }
+    }
+    {
+        const int dH = rEH - f.EH, dP = rEP - f.EP;
+        rM = qldexp(rM, dH); rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rD = qldexp(rD, dH);
+        rgM = qldexp(rgM, dP); rgU = qldexp(rgU, dP); rgD = qldexp(rgD, dP);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float2 e = tab[xo[r] + yc];
+        sm[r].x = e.x * (r == 0 ? f.aD : f.D[r - 1]);
+        sm[r].y = e.y * (r == 0 ? f.gaD : f.gD[r - 1]);
+    }
+    f.oM = sm[R - 1].x;
+    f.ogM = sm[R - 1].y;
+    if (active) {
+        float upM = rM, upU1 = rU1, upU2 = rU2;
+        float gupM = rgM, gupU = rgU;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float nM = sm[r].x, ngM = sm[r].y;
+            const float nU1 = fmaf(k.eps1, upU1, upM);
+            const float nU2 = fmaf(k.eps2, upU2, upM);
+            f.D[r] = fmaf(k.c2, nU2 + f.W2[r], fmaf(k.c1, nU1 + f.W1[r], k.tau * nM));
+            const float ngU = fmaf(k.u, gupU, gupM);
+            f.gD[r] = fmaf(k.o, ngU + f.gW[r], ngM);
+            f.W1[r] = fmaf(k.eps1, f.W1[r], nM);
+            f.W2[r] = fmaf(k.eps2, f.W2[r], nM);
+            f.gW[r] = fmaf(k.u, f.gW[r], ngM);
+            upM = nM; upU1 = nU1; upU2 = nU2;
+            gupM = ngM; gupU = ngU;
+        }
+        f.oU1 = upU1; f.oU2 = upU2;
+        f.ogU = gupU;
+        if (WB && !LAST && lane == L - 1) {
+            FwdBnd<float> b;
+            b.M = f.oM; b.U1 = f.oU1; b.U2 = f.oU2; b.D = f.D[R - 1];
+            b.gM = f.ogM; b.gU = f.ogU; b.gD = f.gD[R - 1];
+            b.EH = f.EH; b.EP = f.EP;
+            fout[j] = b;
+        }
+    }
+    f.aD = rD;
+    f.gaD = rgD;
+}
+
+// power-of-two rescale at a block boundary (as the spilling sweep's)
+template <int R>
+__device__ __forceinline__ void ck_frescale(FwdSt<R>& f) {
+    float mh = 0.f, mp = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        mh = fmaxf(mh, f.D[r]);
+        mp = fmaxf(mp, f.gD[r]);
+    }
+    const int sh = -qexp(mh), sp = -qexp(mp);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        f.W1[r] = qldexp(f.W1[r], sh); f.W2[r] = qldexp(f.W2[r], sh); f.D[r] = qldexp(f.D[r], sh);
+        f.gW[r] = qldexp(f.gW[r], sp); f.gD[r] = qldexp(f.gD[r], sp);
+    }
+    f.oM = qldexp(f.oM, sh); f.oU1 = qldexp(f.oU1, sh); f.oU2 = qldexp(f.oU2, sh);
+    f.aD = qldexp(f.aD, sh); f.tv1 = qldexp(f.tv1, sh); f.tv2 = qldexp(f.tv2, sh);
+    f.ogM = qldexp(f.ogM, sp); f.ogU = qldexp(f.ogU, sp);
+    f.gaD = qldexp(f.gaD, sp); f.tgv = qldexp(f.tgv, sp);
+    f.EH -= sh;
+    f.EP -= sp;
+}
+
+// saved state of one block: word w of lane l at ck[w * kWave + l]
+__device__ __forceinline__ void ck_put(float* ck, int w, int lane, float v) {
+    __builtin_nontemporal_store(v, ck + w * kWave + lane);
+}
+__device__ __forceinline__ float ck_get(const float* ck, int w, int lane) {
+    return __builtin_nontemporal_load(ck + w * kWave + lane);
+}
+template <int R, bool FIRST>
+__device__ __forceinline__ void ck_save(const FwdSt<R>& f, float* ck, int lane) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        ck_put(ck, r, lane, f.W1[r]);
+        ck_put(ck, R + r, lane, f.W2[r]);
+        ck_put(ck, 2 * R + r, lane, f.D[r]);
+        ck_put(ck, 3 * R + r, lane, f.gW[r]);
+        ck_put(ck, 4 * R + r, lane, f.gD[r]);
+    }
+    const int b = 5 * R;
+    ck_put(ck, b + 0, lane, f.oM);
+    ck_put(ck, b + 1, lane, f.oU1);
+    ck_put(ck, b + 2, lane, f.oU2);
+    ck_put(ck, b + 3, lane, f.ogM);
+    ck_put(ck, b + 4, lane, f.ogU);
+    ck_put(ck, b + 5, lane, f.aD);
+    ck_put(ck, b + 6, lane, f.gaD);
+    if (FIRST) {
+        ck_put(ck, b + 7, lane, f.tv1);
+        ck_put(ck, b + 8, lane, f.tv2);
+        ck_put(ck, b + 9, lane, f.tgv);
+    }
+    ck_put(ck, b + 10, lane, __int_as_float(f.EH));
+    ck_put(ck, b + 11, lane, __int_as_float(f.EP));
+}
+template <int R, bool FIRST>
+__device__ __forceinline__ void ck_load(FwdSt<R>& f, const float* ck, int lane) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        f.W1[r] = ck_get(ck, r, lane);
+        f.W2[r] = ck_get(ck, R + r, lane);
+        f.D[r] = ck_get(ck, 2 * R + r, lane);
+        f.gW[r] = ck_get(ck, 3 * R + r, lane);
+        f.gD[r] = ck_get(ck, 4 * R + r, lane);
+    }
+    const int b = 5 * R;
+    f.oM = ck_get(ck, b + 0, lane);
+    f.oU1 = ck_get(ck, b + 1, lane);
+    f.oU2 = ck_get(ck, b + 2, lane);
+    f.ogM = ck_get(ck, b + 3, lane);
+    f.ogU = ck_get(ck, b + 4, lane);
+    f.aD = ck_get(ck, b + 5, lane);
+    f.gaD = ck_get(ck, b + 6, lane);
+    if (FIRST) {
+        f.tv1 = ck_get(ck, b + 7, lane);
+        f.tv2 = ck_get(ck, b + 8, lane);
+        f.tgv = ck_get(ck, b + 9, lane);
+    } else {
+        f.tv1 = f.tv2 = f.tgv = 0.f;
+    }
+    f.EH = __float_as_int(ck_get(ck, b + 10, lane));
+    f.EP = __float_as_int(ck_get(ck, b + 11, lane));
+}
+
+// first sweep of one band: the state at every block start goes to ck, the
+// boundary records of a band above the last to fout; Z from the last band
+template <int R, bool FIRST, bool LAST>
+__device__ void ck_fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* ys, int n, int r0,
+                            int rows, int L, const float2* tab, const Coef<float>& k,
+                            const Col0* __restrict__ col0, float* __restrict__ ck,
+                            const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout, float& zH,
+                            float& zP, int& ezH, int& ezP) {
+    const bool used = lane < L;
+    int xo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = lane * R + r;
+        xo[r] = (used && row < rows ? (int)x[r0 + row] : kPadCode) * kTabW;
+    }
+    FwdSt<R> f;
+    ck_init<R, FIRST, LAST>(f, lane, used, r0, rows, L, k, col0, fin, fout);
+    const int S = n + L - 1;
+    float2 sm[R];
+    int ycn = ys[-lane];
+    for (int s0 = 0, blk = 0; s0 < S; s0 += kRescaleEvery, ++blk) {
+        ck_save<R, FIRST>(f, ck + (int64_t)blk * ck_words(R) * kWave, lane);
+        if (s0 + kRescaleEvery <= S) {
+#pragma unroll
+            for (int q = 0; q < kRescaleEvery; ++q)
+                ck_fstep<R, FIRST, LAST, true>(f, sm, s0 + q, lane, used, n, L, xo, ys, ycn, tab, k, fin, fout);
+            ck_frescale<R>(f);
+        } else {
+            for (int s = s0; s < S; ++s)
+                ck_fstep<R, FIRST, LAST, true>(f, sm, s, lane, used, n, L, xo, ys, ycn, tab, k, fin, fout);
+        }
+    }
+    if (LAST) {
+        const int rm = (rows - 1) - (L - 1) * R;
+        float zd = 0.f, zg = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r == rm) { zd = f.D[r]; zg = f.gD[r]; }
+        zH = rdlane(zd, L - 1);
+        zP = rdlane(zg, L - 1);
+        ezH = rdlane(f.EH, L - 1);
+        ezP = rdlane(f.EP, L - 1);
+    }
+}
+
+// backward sweep of one band with the forward values recomputed per block
+// (a whole block of values held in registers)
+template <int R, bool FIRST, bool LAST>
+__device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* ys, int n, int r0,
+                            int rows, int L, const float2* tab, const Coef<float>& k,
+                            const float* __restrict__ ck, const FwdBnd<float>* __restrict__ fin,
+                            const BwdBnd<float>* __restrict__ bin, BwdBnd<float>* __restrict__ bout, float invZH,
+                            float invZP, int ezH, int ezP, float thresh, int cap, int4* __restrict__ hitlog,
+                            int& nlog, int32_t* __restrict__ rowcnt, int* __restrict__ flags, double& a11) {
+    const bool used = lane < L;
+    int xo[R];
+    bool inrow[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = lane * R + r;
+        inrow[r] = used && row < rows;
+        xo[r] = (inrow[r] ? (int)x[r0 + row] : kPadCode) * kTabW;
+    }
+    float bV1[R], bV2[R], Tp[R], gbV[R], gTp[R];
+    double A[R];
+    int cnt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        bV1[r] = 0.f; bV2[r] = 0.f; Tp[r] = 0.f; gbV[r] = 0.f; gTp[r] = 0.f;
+        A[r] = 0.0;
+        cnt[r] = 0;
+    }
+    int FH = 0, FP = 0;
+    float bT = 0.f, bgT = 0.f;
+    double bA = 0.0;
+    if (LAST && lane == L - 1) {
+        const int rm = (rows - 1) - (L - 1) * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r == rm + 1) { Tp[r] = invZH; gTp[r] = invZP; }
+        if (rm + 1 == R) { bT = invZH; bgT = invZP; }
+    }
+    float oU1 = 0.f, oU2 = 0.f, ogU = 0.f;
+    const int S = n + L - 1;
+    const int lead = L - 1 - lane;
+    BwdBnd<float> bq;
+    if (!LAST && lane == L - 1) bq = bin[n];
+
+    // backward step t with the forward values fc of forward step S-1-t,
+    // whose exponents are ec.  Every lane computes every step: a lane that
+    // has not reached its first column holds zeros and receives zeros, and a
+    // lane past its last column computes values no active lane reads, so
+    // only the hit counts, the logged hits and the band boundary record are
+    // kept to the lane's own columns.
+    int ybn = ys[n + lead - 1];  // residue of the next backward step's column
+    auto bstep = [&](const int t, const float2 (&fc)[R], const int2 ec) {
+        const int j = n - t + lead;
+        const bool active = used && j >= 1 && j <= n;
+        const int yc = ybn;
+        ybn = ys[j - 2];
+        float rU1 = dpp<kDppWaveShl1>(oU1), rU2 = dpp<kDppWaveShl1>(oU2), rT = dpp<kDppWaveShl1>(Tp[0]);
+        float rgU = dpp<kDppWaveShl1>(ogU), rgT = dpp<kDppWaveShl1>(gTp[0]);
+        double rA = dpp<kDppWaveShl1>(A[0]);
+        int rFH = dpp_i<kDppWaveShl1>(FH), rFP = dpp_i<kDppWaveShl1>(FP);
+        if (!LAST) {
+            // lane L-1 of a band above the last takes the lower band's record;
+            // in the last band, lane L-1 reads an unused lane (zeros), which
+            // is what lies below the last row
+            const bool edge = lane == L - 1;
+            rU1 = edge ? bq.U1 : rU1;
+            rU2 = edge ? bq.U2 : rU2;
+            rT = edge ? bq.Tt : rT;
+            rgU = edge ? bq.gU : rgU;
+            rgT = edge ? bq.gT : rgT;
+            rA = edge ? bq.A : rA;
+            rFH = edge ? bq.FH : rFH;
+            rFP = edge ? bq.FP : rFP;
+            if (edge) bq = bin[j - 1 >= 1 ? j - 1 : 1];
+        }
+        {
+            const bool adopt = j >= n && !(LAST && lane == L - 1);
+            const int nFH = adopt ? rFH : FH, nFP = adopt ? rFP : FP;
+            bT = qldexp(bT, FH - nFH);
+            bgT = qldexp(bgT, FP - nFP);
+            FH = nFH;
+            FP = nFP;
+            const int dH = rFH - FH, dP = rFP - FP;
+            rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rT = qldexp(rT, dH);
+            rgU = qldexp(rgU, dP); rgT = qldexp(rgT, dP);
+        }
+        int kbits = 0;  // rows of this step whose hit goes to the log
+        float pv[R];
+        {
+            float dU1 = rU1, dU2 = rU2, dgU = rgU;
+            double dA = rA;
+            float dgT = bT, dggT = bgT;
+            double dgA = bA;
+            const int kH = ec.x + FH - ezH, kP = ec.y + FP - ezP;
+#pragma unroll
+            for (int r = R - 1; r >= 0; --r) {
+                const float2 e = tab[xo[r] + yc];
+                const float t1 = dgT, tg = dggT;
+                const float nU1 = fmaf(k.eps1, dU1, t1);
+                const float nU2 = fmaf(k.eps2, dU2, t1);
+                const float nV1 = fmaf(k.eps1, bV1[r], t1);
+                const float nV2 = fmaf(k.eps2, bV2[r], t1);
+                const float bM = fmaf(k.c2, dU2 + bV2[r], fmaf(k.c1, dU1 + bV1[r], k.tau * t1));
+                const float nT = e.x * bM;
+                const float ngU = fmaf(k.u, dgU, tg);
+                const float ngV = fmaf(k.u, gbV[r], tg);
+                const float gbM = fmaf(k.o, dgU + gbV[r], tg);
+                const float ngT = e.y * gbM;
+                const float pH = qldexp(fc[r].x * bM, kH);
+                const float pP = qldexp(fc[r].y * gbM, kP);
+                const float P = pH + pP;
+                const double nA = fmax(dgA + (double)P, fmax(dA, A[r]));
+                const bool hit = active && inrow[r] && P >= thresh;
+                pv[r] = P;
+                cnt[r] += hit ? 1 : 0;
+                kbits |= hit && cnt[r] <= cap ? (1 << r) : 0;
+                dgT = Tp[r]; dggT = gTp[r]; dgA = A[r];
+                Tp[r] = nT; gTp[r] = ngT; A[r] = nA;
+                bV1[r] = nV1; bV2[r] = nV2; gbV[r] = ngV;
+                dU1 = nU1; dU2 = nU2; dgU = ngU; dA = nA;
+            }
+            oU1 = dU1; oU2 = dU2; ogU = dgU;
+            if (!FIRST && lane == 0 && active) {
+                BwdBnd<float> b;
+                b.U1 = oU1; b.U2 = oU2; b.Tt = Tp[0]; b.gU = ogU; b.gT = gTp[0]; b.A = A[0];
+                b.FH = FH; b.FP = FP;
+                bout[j] = b;
+            }
+        }
+        if (__ballot(kbits != 0)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool keep = ((kbits >> r) & 1) != 0;
+                const unsigned long long km = __ballot(keep);
+                if (km) {
+                    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0));
+                    if (keep)
+                        hitlog[nlog + rank] = make_int4(r0 + lane * R + r, cnt[r] - 1, j - 1, __float_as_int(pv[r]));
+                    nlog = __builtin_amdgcn_readfirstlane(nlog + __popcll(km));
+                }
+            }
+        }
+        bT = rT;
+        bgT = rgT;
+        bA = rA;
+    };
+    auto brescale = [&]() {
+        float mh = 0.f, mp = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            mh = fmaxf(mh, fmaxf(Tp[r], fmaxf(bV1[r], bV2[r])));
+            mp = fmaxf(mp, fmaxf(gTp[r], gbV[r]));
+        }
+        const int sh = -qexp(mh), sp = -qexp(mp);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            bV1[r] = qldexp(bV1[r], sh); bV2[r] = qldexp(bV2[r], sh); Tp[r] = qldexp(Tp[r], sh);
+            gbV[r] = qldexp(gbV[r], sp); gTp[r] = qldexp(gTp[r], sp);
+        }
+        oU1 = qldexp(oU1, sh); oU2 = qldexp(oU2, sh); bT = qldexp(bT, sh);
+        ogU = qldexp(ogU, sp); bgT = qldexp(bgT, sp);
+        FH -= sh;
+        FP -= sp;
+    };
+
+    // one block of kRescaleEvery forward steps, consumed backwards; FULL:
+    // the block has all its steps (no per-step guard, so values stay in
+    // place between steps); the one partial block of a band, the last, is
+    // handled by the guarded instance
+    auto block = [&](const int blk, auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        const int s0 = blk * kRescaleEvery;
+        const int ns = FULL ? kRescaleEvery : min(kRescaleEvery, S - s0);
+        FwdSt<R> f;
+        int ycn = ys[s0 - lane];
+        ck_load<R, FIRST>(f, ck + (int64_t)blk * ck_words(R) * kWave, lane);
+        if (!FIRST && lane == 0) f.bq = fin[min(s0 + 1, n)];
+        const int2 ec = make_int2(f.EH, f.EP);
+        float2 buf[kRescaleEvery][R];
+#pragma unroll
+        for (int q = 0; q < kRescaleEvery; ++q)
+            if (FULL || q < ns)
+                ck_fstep<R, FIRST, LAST, false>(f, buf[q], s0 + q, lane, used, n, L, xo, ys, ycn, tab, k, fin,
+                                                nullptr);
+#pragma unroll
+        for (int q = kRescaleEvery - 1; q >= 0; --q)
+            if (FULL || q < ns) bstep(S - 1 - (s0 + q), buf[q], ec);
+        brescale();
+    };
+    int blk = (S + kRescaleEvery - 1) / kRescaleEvery - 1;
+    if (S % kRescaleEvery != 0) block(blk--, std::false_type{});
+    for (; blk >= 0; --blk) block(blk, std::true_type{});
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = lane * R + r;
+        if (inrow[r]) {
+            int c = cnt[r];
+            if (c > cap) {
+                atomicOr(flags, 2);
+                c = cap;
+            }
+            rowcnt[r0 + row] = c;
+        }
+    }
+    if (FIRST) a11 = rdlane(A[0], 0);
+}
+
+template <int R, bool MULTI>
+__device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, char* slot, const float2* tab, uint8_t* yreg,
+                                const Coef<float>& k, int64_t p) {
+    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
+    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
+    const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
+    const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
+    const uint8_t* x = a.seqs + uniform64(a.seq_off[pi]);
+    const uint8_t* y = a.seqs + uniform64(a.seq_off[pj]);
+    const int H = kWave * R;
+    const int nb = MULTI ? (m + H - 1) / H : 1;
+    // the column sequence into this wave's LDS region, zeros around it (the
+    // wave's reads of the previous pair come before these writes in its
+    // instruction stream)
+    for (int i = lane; i < n + 2 * kYPad; i += kWave) {
+        const int idx = i - kYPad;
+        yreg[i] = idx >= 0 && idx < n ? y[idx] : (uint8_t)0;
+    }
+    const uint8_t* ys = yreg + kYPad;
+    float* ck = reinterpret_cast<float*>(slot);
+    FwdBnd<float>* fb = reinterpret_cast<FwdBnd<float>*>(slot + a.off_fb);
+    BwdBnd<float>* bb = reinterpret_cast<BwdBnd<float>*>(slot + a.off_bb);
+    int4* hitlog = reinterpret_cast<int4*>(slot + a.off_log);
+    int nlog = 0;
+    float zH = 1.f, zP = 1.f;
+    int ezH = 0, ezP = 0;
+    const Col0* col0 = reinterpret_cast<const Col0*>(a.col0);
+    // every band keeps its forward boundary records: the band below reads
+    // them again when it recomputes its blocks in the backward sweep
+    for (int b = 0; b < nb; ++b) {
+        const int r0 = b * H;
+        const int rows = min(H, m - r0);
+        const int L = (rows + R - 1) / R;
+        float* c = ck + (int64_t)b * a.spill_band_stride;
+        const FwdBnd<float>* fi = fb + (int64_t)(b > 0 ? b - 1 : 0) * a.bnd_stride;
+        FwdBnd<float>* fo = fb + (int64_t)b * a.bnd_stride;
+        if (!MULTI)
+            ck_fwd_band<R, true, true>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
+        else if (b == 0)
+            ck_fwd_band<R, true, false>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
+        else if (b == nb - 1)
+            ck_fwd_band<R, false, true>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
+        else
+            ck_fwd_band<R, false, false>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
+        __threadfence_block();
+    }
+    const float invZH = (float)a.consts->w_hmm / zH;
+    const float invZP = (float)(1.0 - a.consts->w_hmm) / zP;
+    int32_t* rp = a.row_ptr + a.row_off[p];
+    double a11 = 0.0;
+    for (int b = nb - 1; b >= 0; --b) {
+        const int r0 = b * H;
+        const int rows = min(H, m - r0);
+        const int L = (rows + R - 1) / R;
+        const float* c = ck + (int64_t)b * a.spill_band_stride;
+        const FwdBnd<float>* fi = fb + (int64_t)(b > 0 ? b - 1 : 0) * a.bnd_stride;
+        const BwdBnd<float>* bi = bb + (int64_t)((b + 1) & 1) * a.bnd_stride;
+        BwdBnd<float>* bo = bb + (int64_t)(b & 1) * a.bnd_stride;
+#define QP_CKB(F, Lb)                                                                                          \
+    ck_bwd_band<R, F, Lb>(lane, x, ys, n, r0, rows, L, tab, k, c, fi, bi, bo, invZH, invZP, ezH, ezP, a.thresh, \
+                          a.cap, hitlog, nlog, rp + 1, a.flags, a11)
+        if (!MULTI)
+            QP_CKB(true, true);
+        else if (b == 0)
+            QP_CKB(true, false);
+        else if (b == nb - 1)
+            QP_CKB(false, true);
+        else
+            QP_CKB(false, false);
+#undef QP_CKB
+        __threadfence_block();
+    }
+    finish_pair(a, lane, p, m, n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
+}
+
+template <int R, bool MULTI>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs_ck(PairArgs a) {
+    __shared__ float2 tab[kTabRows * kTabW];
+    __shared__ uint8_t ysh[kWavesPerBlock * kYStride];
+    const float2* gtab = reinterpret_cast<const float2*>(a.tab);
+    for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    char* slot = a.scratch + (int64_t)wid * a.slot_bytes;
+    const DevConsts c = *a.consts;
+    Coef<float> k;
+    k.tau = (float)c.tau; k.eps1 = (float)c.eps1; k.eps2 = (float)c.eps2; k.c1 = (float)c.c1; k.c2 = (float)c.c2;
+    k.u = (float)c.u; k.o = (float)c.o;
+    const int k0 = a.cls * kCostBins, k1 = k0 + kCostBins - 1;
+    const int seg_begin = __builtin_amdgcn_readfirstlane(a.bin_start[k1]);
+    const int seg_end = __builtin_amdgcn_readfirstlane(a.bin_start[k0] + a.hist[k0]);
+    int* head = a.queue_head + a.cls;
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(head, 1);
+        q = __builtin_amdgcn_readfirstlane(q) + seg_begin;
+        if (q >= seg_end) break;
+        const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
+        process_pair_ck<R, MULTI>(a, lane, slot, tab, ysh + (threadIdx.x >> 6) * kYStride, k, p);
+    }
+}
+
+template <int R, bool MULTI>
+__global__ __launch_bounds__(kWave) void k_pair_one_ck(PairArgs a, int64_t p) {
+    __shared__ float2 tab[kTabRows * kTabW];
+    __shared__ uint8_t ysh[kYStride];
+    const float2* gtab = reinterpret_cast<const float2*>(a.tab);
+    for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const DevConsts c = *a.consts;
+    Coef<float> k;
+    k.tau = (float)c.tau; k.eps1 = (float)c.eps1; k.eps2 = (float)c.eps2; k.c1 = (float)c.c1; k.c2 = (float)c.c2;
+    k.u = (float)c.u; k.o = (float)c.o;
+    process_pair_ck<R, MULTI>(a, lane, a.scratch, tab, ysh, k, p);
 }
 
 // ------------------------------------------------------ tables (a2 step)
@@ -1146,6 +1776,66 @@ hipError_t launch_pair_one(int cls, int fp64, int64_t p, const PairArgs& a, hipS
         default: return launch_pair_one_r<8, true>(fp64, p, a, s);
     }
 }
+
+template <int R, bool MULTI>
+static hipError_t launch_pairs_ck_r(int grid, const PairArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_pairs_ck<R, MULTI>), dim3(grid), dim3(kWave * kWavesPerBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// The checkpointed form exists for classes of 1..kCkMaxRows rows per lane:
+// beyond that the routine does not fit the registers, the compiler stops
+// inlining it into the kernel (a called function, its arguments through a
+// stack in scratch memory) and such a kernel faulted the GPU with the cause
+// not identified, so it is not built.
+hipError_t launch_pairs_ck(int cls, int grid, const PairArgs& a, hipStream_t s) {
+    switch (cls) {
+        case 0: return launch_pairs_ck_r<1, false>(grid, a, s);
+        case 1: return launch_pairs_ck_r<2, false>(grid, a, s);
+        case 2: return launch_pairs_ck_r<3, false>(grid, a, s);
+        case 3: return launch_pairs_ck_r<4, false>(grid, a, s);
+        case 4: return launch_pairs_ck_r<5, false>(grid, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int R, bool MULTI>
+static hipError_t launch_pair_one_ck_r(int64_t p, const PairArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_one_ck<R, MULTI>), dim3(1), dim3(kWave), 0, s, a, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_one_ck(int cls, int64_t p, const PairArgs& a, hipStream_t s) {
+    switch (cls) {
+        case 0: return launch_pair_one_ck_r<1, false>(p, a, s);
+        case 1: return launch_pair_one_ck_r<2, false>(p, a, s);
+        case 2: return launch_pair_one_ck_r<3, false>(p, a, s);
+        case 3: return launch_pair_one_ck_r<4, false>(p, a, s);
+        case 4: return launch_pair_one_ck_r<5, false>(p, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int R, bool MULTI>
+static int blocks_per_cu_ck_r() {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pairs_ck<R, MULTI>,
+                                                                kWave * kWavesPerBlock, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+int pairs_ck_blocks_per_cu(int cls) {
+    switch (cls) {
+        case 0: return blocks_per_cu_ck_r<1, false>();
+        case 1: return blocks_per_cu_ck_r<2, false>();
+        case 2: return blocks_per_cu_ck_r<3, false>();
+        case 3: return blocks_per_cu_ck_r<4, false>();
+        case 4: return blocks_per_cu_ck_r<5, false>();
+        default: return 1;
+    }
+}
+
+int ck_state_words(int R) { return ck_words(R); }
 
 template <int R, bool MULTI>
 static int blocks_per_cu_r(int fp64) {

@@ -118,6 +118,16 @@ hipError_t launch_pairs(int cls, int fp64, int grid, const PairArgs& a, hipStrea
 // the plain per-pair form: pair p alone, one wave, scratch slot 0 of a.scratch
 hipError_t launch_pair_one(int cls, int fp64, int64_t p, const PairArgs& a, hipStream_t s);
 int pairs_blocks_per_cu(int cls, int fp64);
+// checkpointed FP32 form of the pair kernels (forward values recomputed per
+// block in the backward sweep instead of spilled); a slot holds, per band,
+// the saved forward state of every block (ck_state_words(R) words per lane)
+// in place of the spilled values and exponents, and the forward boundary
+// records of every band
+constexpr int kCkMaxClass = 4;  // classes 0..4 (1..5 rows per lane) have the form
+hipError_t launch_pairs_ck(int cls, int grid, const PairArgs& a, hipStream_t s);
+hipError_t launch_pair_one_ck(int cls, int64_t p, const PairArgs& a, hipStream_t s);
+int pairs_ck_blocks_per_cu(int cls);
+int ck_state_words(int R);
 hipError_t launch_gather(int64_t n_pairs, const int64_t* nnz_off, const int64_t* pair_base, const int32_t* pool_col, const float* pool_val,
                          int32_t* col, float* val, int64_t cap, hipStream_t s);
 size_t fwd_bnd_bytes(int fp64);
@@ -168,9 +178,10 @@ int alphabet_of(const qp_params* p);               // residue codes 0..alphabet-
 int64_t row_bound(int32_t cols, float thresh);     // slots of one output row
 qp_status validate_lens(const int32_t* lens, int32_t n);
 qp_status check_device(int* dev, int* n_cu);       // current device is gfx950
-void current_tuning(ClassMap* map, double* waves_frac);  // the tuning table in force
+void current_tuning(ClassMap* map, double* waves_frac, int* recompute);  // the tuning table in force
 // layout of one per-wave scratch slot of a kernel class with R rows per lane,
-// at most mmax rows, nmax columns and nb_max bands, cap output slots per row
-void slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, PairArgs* a);
+// at most mmax rows, nmax columns and nb_max bands, cap output slots per row;
+// ck: the checkpointed form's layout
+void slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, bool ck, PairArgs* a);
 
 }  // namespace qp

@@ -155,7 +155,8 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
     // shape of the work per kernel class (as a plan sized to the bound)
     qp::ClassMap cmap{};
     double frac[qp::kClasses];
-    qp::current_tuning(&cmap, frac);
+    int recompute[qp::kClasses];
+    qp::current_tuning(&cmap, frac, recompute);
     struct Cls {
         int64_t pairs = 0;
         int mmax = 1, nmax = 1;
@@ -189,6 +190,7 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
     const int fp64 = params->precision == QP_FP64 ? 1 : 0;
     const double inv = std::floor(1.0 / (double)thresh);
     qp::PairArgs cargs[qp::kClasses];
+    bool ck[qp::kClasses] = {};
     int64_t slot_max = 0;
     for (int c = 0; c < qp::kClasses; ++c) {
         if (!cls[c].pairs) continue;
@@ -197,7 +199,8 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
         const int nb = c == qp::kRMax ? (cls[c].mmax + H - 1) / H : 1;
         const int cap = (int)std::max(1.0, std::min((double)cls[c].nmax, inv + 1.0));
         cargs[c] = qp::PairArgs{};
-        qp::slot_layout(R, cls[c].mmax, cls[c].nmax, nb, cap, fp64, &cargs[c]);
+        ck[c] = !fp64 && recompute[c] != 0;
+        qp::slot_layout(R, cls[c].mmax, cls[c].nmax, nb, cap, fp64, ck[c], &cargs[c]);
         cargs[c].cap = cap;
         slot_max = std::max(slot_max, cargs[c].slot_bytes);
     }
@@ -316,11 +319,14 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
         // waves of this class: its occupancy-limited grid, its pair count and
         // the slots that fit in the workspace (the slot area is reused by the
         // next class, which starts after this one on the same stream)
-        const int per_cu = qp::pairs_blocks_per_cu(c, fp64);
+        const int per_cu = ck[c] ? qp::pairs_ck_blocks_per_cu(c) : qp::pairs_blocks_per_cu(c, fp64);
         int64_t grid = std::max<int64_t>(1, (int64_t)std::llround(per_cu * n_cu * frac[c]));
         grid = std::min<int64_t>(grid, (cls[c].pairs + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock);
         grid = std::min<int64_t>(grid, slots / qp::kWavesPerBlock);
-        NA_TRY(qp::launch_pairs(c, fp64, (int)grid, ca, s));
+        if (ck[c])
+            NA_TRY(qp::launch_pairs_ck(c, (int)grid, ca, s));
+        else
+            NA_TRY(qp::launch_pairs(c, fp64, (int)grid, ca, s));
     }
     NA_TRY(qp::scan_i64(out->nnz_off, P + 1, d_scan_tmp, s));
     NA_TRY(qp::launch_gather(P, out->nnz_off, d_base, d_pool_col, d_pool_val, out->col, out->val, bound, s));

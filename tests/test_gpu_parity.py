@@ -425,7 +425,48 @@ def test_tuned_class_map(B, params, shift):
                     _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
                     k += 1
     finally:
-        B.set_tuning(before["rows_per_lane"], before["waves_frac"])
+        B.set_tuning(before["rows_per_lane"], before["waves_frac"], before["recompute"])
+
+
+_CK_OFF = pytest.mark.skip(reason="the checkpointed form for 6+ rows per lane compiled into a called (not inlined) "
+                                  "routine and faulted the GPU with the cause not identified; it is not built")
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4, 5, pytest.param(6, marks=_CK_OFF), pytest.param(7, marks=_CK_OFF),
+                               pytest.param(8, marks=_CK_OFF)])
+def test_recompute_form(B, params, R):
+    """The checkpointed form (forward values recomputed per 8-step block in
+    the backward sweep) against the spilling form and the oracle, on pairs
+    whose row sequences need R rows per lane (partial blocks, lane edges and
+    a single-column pair included)."""
+    rng = np.random.default_rng(100 + R)
+    lo, hi = 64 * (R - 1) + 1, 64 * R
+    rows = [lo, hi, int(rng.integers(lo, hi + 1))]
+    cols = [1, 7, 64 * R, int(rng.integers(50, 700)), int(rng.integers(50, 700))]
+    fam = W.make_family(len(rows) + len(cols), rows + cols, 200 + R, r_sub=0.3, r_indel=0.05)
+    pi = np.array([i for i in range(len(rows)) for _ in cols], dtype=np.int32)
+    pj = np.array([len(rows) + c for _ in rows for c in range(len(cols))], dtype=np.int32)
+    before = B.get_tuning()
+    out = {}
+    try:
+        for form in (0, 1):
+            B.set_tuning(recompute=[form] * 5 + [0] * 4)
+            out[form] = B.qp_posteriors_pairs(fam, pi, pj, B.make_params(params, 0), 0.01)
+    finally:
+        B.set_tuning(before["rows_per_lane"], before["waves_frac"], before["recompute"])
+    a, b = out[0], out[1]
+    assert np.array_equal(a["nnz_off"], b["nnz_off"]) and np.array_equal(a["col"], b["col"])
+    assert np.array_equal(a["row_ptr"], b["row_ptr"])
+    d = np.abs(a["val"].astype(np.float64) - b["val"])
+    _say("R=%d: %d entries, %d differ, max |d| %.3g; EA max |d| %.3g" % (
+        R, len(d), int((d > 0).sum()), d.max(initial=0.0), np.abs(a["dist"] - b["dist"]).max()))
+    assert d.max(initial=0.0) <= 1e-6
+    assert np.abs(a["dist"] - b["dist"]).max() <= 1e-6
+    assert np.array_equal(a["log_z"], b["log_z"])
+    for k in range(len(pi)):
+        x, y = fam[pi[k]], fam[pj[k]]
+        orc = oracle.pair(x, y, params, per_model=False)
+        _check_pair(b, k, x, y, orc, 0.01, TOL[0])
 
 
 def test_plan_sized_to_output_bound(B, params):
