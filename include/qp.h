@@ -404,6 +404,57 @@ qp_status qp_guide_tree(const double* dist, int32_t n, int32_t* merges, double* 
 qp_status qp_tree_distance(const int32_t* merges, int32_t n, int32_t* out);
 
 /* ------------------------------------------------------------------------
+ * Selective consistency (the stage that consumes the posteriors and the
+ * guide tree; paper: Methods, "Selective consistency", and "Other
+ * algorithmic improvements" for the number of passes).  Every pair's sparse
+ * matrix is relaxed through the third sequences z the tree selects:
+ *   Z_xy  = { z not x, y : max(d_xz, d_yz) <= tree_threshold }  (tree-guided
+ *           distances as qp_tree_distance gives them)
+ *   h_xy  = 1 + (amplification - 1) |Z_xy| / (n - 2)   (1 when n = 2)
+ *   S'_xy = (2 h_xy S_xy + sum over z in Z_xy of S_xz S_zy) / (2 h_xy + |Z_xy|)
+ * with S_ab = S_ba transposed for a > b, entries below thresh dropped; each
+ * pass relaxes every pair from the previous pass's matrices (the paper uses
+ * two passes below 50 sequences, one otherwise; T about 200, amplification
+ * 3).  Device memory, the caller's stream; FP32 accumulation.
+ * ---------------------------------------------------------------------- */
+typedef struct qp_relax qp_relax;
+
+/*
+ * Workspace for one family shape (all pairs i < j of n sequences).
+ *   lens[n]         host sequence lengths (validated as for qp_plan_create)
+ *   in_capacity     entries of the input CSR it will be given (0: the
+ *                   output bound of the family at thresh, see
+ *                   qp_output_bound); the relaxed outputs are sized to that
+ *                   bound, so no pass can overflow
+ * QP_EINVAL for n > 2048, a negative threshold, amplification < 1, passes
+ * outside [1, 8] or thresh outside (0, 1]; QP_ENOMEM when the workspace
+ * cannot be allocated.
+ */
+qp_status qp_relax_create(const int32_t* lens, int32_t n, int64_t in_capacity, int32_t tree_threshold,
+                          double amplification, int32_t passes, float thresh, qp_relax** relax);
+
+/* Enqueue every pass on `stream`.  in: device CSR of all pairs in the
+ * layout of qp_device_result (for instance what qp_plan_sync returns for an
+ * all-pairs plan), holding in_nnz entries; d_tdist: device int32 [n(n-1)/2]
+ * tree-guided distances in pair order.  Inputs are read during the run.
+ * One run at a time per workspace (a new run waits for the last). */
+qp_status qp_relax_run(qp_relax* relax, const qp_device_result* in, int64_t in_nnz, const int32_t* d_tdist,
+                       void* stream);
+
+/* Wait for the run and fill *out (may be NULL) with device pointers into
+ * workspace-owned outputs (layout of qp_device_result), valid until the next
+ * run or qp_relax_destroy. */
+qp_status qp_relax_sync(qp_relax* relax, qp_device_result* out);
+
+/* Copy the relaxed matrices to a library-owned host result (qp_result_free). */
+qp_status qp_relax_download(qp_relax* relax, qp_result** out);
+
+/* Device bytes held by the workspace. */
+int64_t qp_relax_device_bytes(const qp_relax* relax);
+
+void qp_relax_destroy(qp_relax* relax);
+
+/* ------------------------------------------------------------------------
  * Serving: families arrive over time; each is admitted when the free device
  * memory budget covers its workspace and outputs and a slot is free; admitted
  * families run concurrently on a pool of streams (continuous batching), and

@@ -121,6 +121,14 @@ SIGNATURES = {
     "qp_get_tuning": (ctypes.c_int, [_P(qp_tuning)]),
     "qp_posteriors_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _P(ctypes.c_int32), ctypes.c_int32,
                                              _P(qp_params), ctypes.c_float, _P(qp_noalloc_out), ctypes.c_void_p]),
+    "qp_relax_create": (ctypes.c_int, [_P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.c_float, _P(ctypes.c_void_p)]),
+    "qp_relax_run": (ctypes.c_int, [ctypes.c_void_p, _P(qp_device_result), ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "qp_relax_sync": (ctypes.c_int, [ctypes.c_void_p, _P(qp_device_result)]),
+    "qp_relax_download": (ctypes.c_int, [ctypes.c_void_p, _P(_P(qp_result))]),
+    "qp_relax_device_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "qp_relax_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -465,6 +473,58 @@ def posteriors_noalloc(d_seqs_ptr: int, d_off_ptr: int, lens, params: qp_params,
     _check(lib.qp_posteriors_noalloc(ctypes.c_void_p(d_seqs_ptr), ctypes.c_void_p(d_off_ptr),
                                      lens.ctypes.data_as(_P(ctypes.c_int32)), len(lens), ctypes.byref(params),
                                      ctypes.c_float(thresh), ctypes.byref(o), ctypes.c_void_p(stream_ptr)))
+
+
+def device_result(n_pairs: int, total_rows: int, nnz: int, ptrs: Dict[str, int]) -> qp_device_result:
+    """qp_device_result over caller-owned device arrays (pair_i, pair_j,
+    row_off, row_ptr, nnz_off, col, val; dist and log_z optional)."""
+    r = qp_device_result()
+    r.n_pairs, r.total_rows, r.nnz = int(n_pairs), int(total_rows), int(nnz)
+    for name in ("pair_i", "pair_j", "row_off", "row_ptr", "nnz_off", "col", "val", "dist", "log_z"):
+        setattr(r, name, ctypes.c_void_p(int(ptrs.get(name, 0))))
+    return r
+
+
+class Relax:
+    """Selective consistency on the device (qp_relax_*): relaxes the all-pairs
+    CSR of a family through the third sequences the guide tree selects."""
+
+    def __init__(self, lens: Sequence[int], tree_threshold: int, amplification: float, passes: int, thresh: float,
+                 in_capacity: int = 0):
+        self._lens = np.ascontiguousarray(lens, dtype=np.int32)
+        self.handle = ctypes.c_void_p()
+        _check(lib.qp_relax_create(self._lens.ctypes.data_as(_P(ctypes.c_int32)), len(self._lens),
+                                   int(in_capacity), int(tree_threshold), float(amplification), int(passes),
+                                   ctypes.c_float(thresh), ctypes.byref(self.handle)))
+
+    def run(self, dev_in: qp_device_result, in_nnz: int, d_tdist_ptr: int, stream_ptr: int):
+        self._in = dev_in  # read during the run
+        _check(lib.qp_relax_run(self.handle, ctypes.byref(dev_in), int(in_nnz), ctypes.c_void_p(d_tdist_ptr),
+                                ctypes.c_void_p(stream_ptr)))
+
+    def sync(self) -> qp_device_result:
+        r = qp_device_result()
+        _check(lib.qp_relax_sync(self.handle, ctypes.byref(r)))
+        return r
+
+    def download(self) -> Dict[str, np.ndarray]:
+        out = _P(qp_result)()
+        _check(lib.qp_relax_download(self.handle, ctypes.byref(out)))
+        return _take_result(out)
+
+    def device_bytes(self) -> int:
+        return int(lib.qp_relax_device_bytes(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib.qp_relax_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_inputs(seqs: Sequence[np.ndarray], device: str = "cuda:0"):

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqp.so")
-SOURCES = ["qp_device.hip", "qp_noalloc.hip", "qp_api.cpp", "qp_server.cpp", "qp_host.cpp", "qp_tree.cpp"]
+SOURCES = ["qp_device.hip", "qp_noalloc.hip", "qp_relax.hip", "qp_api.cpp", "qp_server.cpp", "qp_host.cpp", "qp_tree.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no v_pk_*_f32 in any generated code

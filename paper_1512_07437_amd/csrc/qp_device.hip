@@ -32,6 +32,7 @@
 #include <type_traits>
 
 #include "qp_internal.h"
+#include "qp_wave.h"
 
 namespace qp {
 
@@ -120,14 +121,6 @@ __device__ __forceinline__ double pow2s(double lg, int e, int sh) {
     return e == 0 ? exp2(-(double)sh) : exp2((double)e * lg - (double)sh);
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
 
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
     const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
@@ -1492,29 +1485,6 @@ __global__ void k_reset(int* ints, int n) {
 }
 
 __device__ __forceinline__ int64_t pair_start(int64_t i, int64_t n) { return i * n - i * (i + 1) / 2; }
-// counter[k] += 1 for every lane with `valid`, with one atomic per distinct k
-// in the wavefront (the lanes of a wave mostly share a key, so per-lane
-// atomics on a few addresses would serialise); returns the lane's 0-based
-// position among all additions to counter[k].  Uniform control flow: every
-// lane of the wave must call it.
-__device__ __forceinline__ int wave_count_add(int* counter, int k, bool valid) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    unsigned long long todo = __ballot(valid);
-    int slot = 0;
-    while (todo) {
-        const int leader = __builtin_ctzll(todo);
-        const int lk = __shfl(k, leader, kWave);
-        const bool mine = valid && k == lk;
-        const unsigned long long same = __ballot(mine);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&counter[lk], __popcll(same));
-        base = __shfl(base, leader, kWave);
-        if (mine) slot = base + __popcll(same & below);
-        todo &= ~same;
-    }
-    return slot;
-}
 
 
 // 4-byte aligned, zero padded copy of every sequence; codes outside the

@@ -1,0 +1,515 @@
+// Selective consistency on the device: every pair's sparse posterior matrix
+// is relaxed through the third sequences the guide tree selects (paper:
+// Methods, "Selective consistency"; "Other algorithmic improvements" for the
+// number of passes).  For pair (x, y) with Z_xy = { z : max(d_xz, d_yz) <= T }
+// (tree-guided distances) and h_xy = 1 + (h - 1) |Z_xy| / (k - 2):
+//   S'_xy = (2 h_xy S_xy + sum_{z in Z_xy} S_xz S_zy) / (2 h_xy + |Z_xy|),
+// entries below the sparsity threshold dropped; S_ab for a > b is S_ba
+// transposed.  The paper names the transformation, its selection rule, the
+// amplification and the pass count; the formula is the consistency
+// transformation of the aligners the method descends from, read as above.
+//
+// Layout: the all-pairs CSR of the posterior stage (qp_device_result).  Per
+// pass: (1) every pair's matrix is transposed into a CSR of the same entry
+// range (rows = residues of the second sequence), so both orientations of
+// every S_ab are rows of some CSR; (2) one wavefront per pair accumulates
+// each output row in LDS -- lanes take the selected z's, walk row i of S_xz
+// and, for each of its entries (k, v), row k of S_zy, adding v * S_zy(k, j)
+// with LDS atomics -- then scales, thresholds and compacts the row in
+// column order; (3) per-pair counts are scanned and the entries gathered in
+// pair order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qp.h"
+#include "qp_internal.h"
+#include "qp_wave.h"
+
+namespace {
+
+using qp::kWave;
+constexpr int kRelaxWaves = 4;       // wavefronts per block
+constexpr int kMaxRelaxSeqs = 2048;  // the selection of a pair is a 32-bit mask per lane
+
+struct Csr {
+    const int64_t* row_off;  // [P + 1] into row_ptr
+    const int32_t* row_ptr;  // per pair: rows + 1 local pointers
+    const int64_t* nnz_off;  // [P + 1] into col / val
+    const int32_t* col;
+    const float* val;
+};
+
+__device__ __forceinline__ int64_t pidx(int64_t a, int64_t b, int64_t k) { return a * k - a * (a + 1) / 2 + (b - a - 1); }
+
+// transposes of every pair's matrix; the transposed rows of pair p are the
+// columns of its second sequence, its entries occupy the same range of
+// tr_col / tr_val as the pair's own, rows ascending within a column
+__global__ __launch_bounds__(kWave * kRelaxWaves) void k_transpose(
+    int32_t k, int64_t P, const int32_t* __restrict__ lens, const int32_t* __restrict__ pair_i,
+    const int32_t* __restrict__ pair_j, Csr in, const int64_t* __restrict__ tr_row_off,
+    int32_t* __restrict__ tr_row_ptr, int32_t* __restrict__ tr_col, float* __restrict__ tr_val,
+    int* __restrict__ flags) {
+    __shared__ int cnt_s[kRelaxWaves][qp::kMaxSeqLen + 1];
+    __shared__ int rp_s[kRelaxWaves][qp::kMaxSeqLen + 1];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int* cnt = cnt_s[w];
+    int* rp = rp_s[w];
+    for (int64_t p = (int64_t)blockIdx.x * kRelaxWaves + w; p < P; p += (int64_t)gridDim.x * kRelaxWaves) {
+        const int a = __builtin_amdgcn_readfirstlane(pair_i[p]);
+        const int b = __builtin_amdgcn_readfirstlane(pair_j[p]);
+        const int m = lens[a], n = lens[b];
+        const int64_t base = in.nnz_off[p];
+        const int ne = (int)(in.nnz_off[p + 1] - base);
+        const int32_t* rpi = in.row_ptr + in.row_off[p];
+        int32_t* rpo = tr_row_ptr + tr_row_off[p];
+        for (int c = lane; c <= n; c += kWave) cnt[c] = 0;
+        // an entry whose column lies outside the second sequence is left out
+        // (and reported), so that nothing is written outside the pair's range
+        for (int e0 = 0; e0 < ne; e0 += kWave) {
+            const int e = e0 + lane;
+            const int j = e < ne ? in.col[base + e] : 0;
+            const bool valid = e < ne && j >= 0 && j < n;
+            if (e < ne && !valid) atomicOr(flags, 4);
+            qp::wave_count_add(cnt, valid ? j : 0, valid);
+        }
+        int carry = 0;
+        for (int c0 = 0; c0 <= n; c0 += kWave) {
+            const int c = c0 + lane;
+            const int v = c < n ? cnt[c] : 0;
+            const int inc = qp::wave_incl_scan(v, lane);
+            if (c <= n) {
+                rp[c] = carry + inc - v;
+                rpo[c] = carry + inc - v;
+            }
+            carry += __shfl(inc, kWave - 1, kWave);
+        }
+        for (int c = lane; c <= n; c += kWave) cnt[c] = 0;
+        for (int e0 = 0; e0 < ne; e0 += kWave) {
+            const int e = e0 + lane;
+            const int jr = e < ne ? in.col[base + e] : 0;
+            const bool valid = e < ne && jr >= 0 && jr < n;
+            const int j = valid ? jr : 0;
+            // row of entry e: the last i with rpi[i] <= e (rpi[0] = 0, rpi[m] = ne)
+            int lo = 0, hi = m;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rpi[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            // entries are met in row order, so ranks within a column ascend with the row
+            const int rank = qp::wave_count_add(cnt, j, valid);
+            if (valid) {
+                tr_col[base + rp[j] + rank] = lo;
+                tr_val[base + rp[j] + rank] = in.val[base + e];
+            }
+        }
+    }
+}
+
+// one pass of the relaxation; out_* receive per-pair row pointers and the
+// kept entries at the pair's bound offset (stage_off), out_nnz the count
+__global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
+    int32_t k, int64_t P, const int32_t* __restrict__ lens, const int32_t* __restrict__ pair_i,
+    const int32_t* __restrict__ pair_j, Csr in, const int64_t* __restrict__ tr_row_off,
+    const int32_t* __restrict__ tr_row_ptr, const int32_t* __restrict__ tr_col, const float* __restrict__ tr_val,
+    const int32_t* __restrict__ tdist, int32_t T, float h, float thresh, int32_t cap,
+    const int64_t* __restrict__ out_row_off, int32_t* __restrict__ out_row_ptr, const int64_t* __restrict__ stage_off,
+    int32_t* __restrict__ stage_col, float* __restrict__ stage_val, int64_t* __restrict__ out_nnz,
+    int* __restrict__ flags) {
+    __shared__ float acc_s[kRelaxWaves][qp::kMaxSeqLen];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    float* acc = acc_s[w];
+    for (int64_t p = (int64_t)blockIdx.x * kRelaxWaves + w; p < P; p += (int64_t)gridDim.x * kRelaxWaves) {
+        const int x = __builtin_amdgcn_readfirstlane(pair_i[p]);
+        const int y = __builtin_amdgcn_readfirstlane(pair_j[p]);
+        const int m = lens[x], n = lens[y];
+        // selection: bit c of a lane's mask is z = 64 c + lane
+        uint32_t sel = 0;
+        int nsel = 0;
+        for (int c = 0; c * kWave < k; ++c) {
+            const int z = c * kWave + lane;
+            bool s = z < k && z != x && z != y;
+            if (s) {
+                const int dxz = tdist[pidx(min(x, z), max(x, z), k)];
+                const int dyz = tdist[pidx(min(y, z), max(y, z), k)];
+                s = max(dxz, dyz) <= T;
+            }
+            sel |= s ? (1u << c) : 0u;
+            nsel += __popcll(__ballot(s));
+        }
+        const float hxy = k <= 2 ? 1.f : 1.f + (h - 1.f) * (float)nsel / (float)(k - 2);
+        const float own = 2.f * hxy;
+        const float invW = 1.f / (2.f * hxy + (float)nsel);
+        const int64_t bxy = in.nnz_off[p];
+        const int32_t* rxy = in.row_ptr + in.row_off[p];
+        int32_t* orp = out_row_ptr + out_row_off[p];
+        const int64_t obase = stage_off[p];
+        int count = 0;
+        for (int i = 0; i < m; ++i) {
+            for (int c = lane; c < n; c += kWave) acc[c] = 0.f;
+            for (int e = rxy[i] + lane; e < rxy[i + 1]; e += kWave) {
+                const int j = in.col[bxy + e];
+                if (j >= 0 && j < n) acc[j] = own * in.val[bxy + e];
+            }
+            for (int c = 0; c * kWave < k; ++c) {
+                if (!((sel >> c) & 1u)) continue;
+                const int z = c * kWave + lane;
+                // row i of S_xz: pair (x, z) as stored, or (z, x) transposed
+                const bool xa = x < z;
+                const int64_t pxz = xa ? pidx(x, z, k) : pidx(z, x, k);
+                const int32_t* ra = xa ? in.row_ptr + in.row_off[pxz] : tr_row_ptr + tr_row_off[pxz];
+                const int32_t* ca = xa ? in.col : tr_col;
+                const float* va = xa ? in.val : tr_val;
+                const int64_t ba = in.nnz_off[pxz];
+                // rows of S_zy: pair (z, y) as stored, or (y, z) transposed
+                const bool za = z < y;
+                const int64_t pzy = za ? pidx(z, y, k) : pidx(y, z, k);
+                const int32_t* rb = za ? in.row_ptr + in.row_off[pzy] : tr_row_ptr + tr_row_off[pzy];
+                const int32_t* cb = za ? in.col : tr_col;
+                const float* vb = za ? in.val : tr_val;
+                const int64_t bb = in.nnz_off[pzy];
+                for (int ea = ra[i]; ea < ra[i + 1]; ++ea) {
+                    const int kk = ca[ba + ea];
+                    const float v1 = va[ba + ea];
+                    for (int eb = rb[kk]; eb < rb[kk + 1]; ++eb) {
+                        const int j = cb[bb + eb];
+                        if (j >= 0 && j < n) atomicAdd(&acc[j], v1 * vb[bb + eb]);
+                    }
+                }
+            }
+            // scale, threshold, compact in column order (at most cap per row)
+            int rc = 0;
+            for (int c0 = 0; c0 < n; c0 += kWave) {
+                const int c = c0 + lane;
+                const float v = c < n ? acc[c] * invW : 0.f;
+                const bool hit = c < n && v >= thresh;
+                const unsigned long long hm = __ballot(hit);
+                const int rank = rc + __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (kWave - lane))));
+                if (hit && rank < cap) {
+                    stage_col[obase + count + rank] = c;
+                    stage_val[obase + count + rank] = v;
+                }
+                rc += __popcll(hm);
+            }
+            if (rc > cap) {
+                if (lane == 0) atomicOr(flags, 2);
+                rc = cap;
+            }
+            count += rc;
+            if (lane == 0) orp[i + 1] = count;
+        }
+        if (lane == 0) {
+            orp[0] = 0;
+            out_nnz[p] = count;
+        }
+    }
+}
+
+__global__ void k_zero_i32(int* __restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+}  // namespace
+
+struct qp_relax {
+    int device = 0;
+    int32_t k = 0;
+    int64_t P = 0;
+    int32_t T = 0;
+    double h = 1.0;
+    int32_t passes = 1;
+    float thresh = 0.f;
+    int32_t cap = 1;
+    int n_cu = 1;
+    std::vector<int32_t> lens;
+    int64_t total_rows = 0, tr_rows = 0, bound = 0, in_cap = 0;
+    std::vector<void*> allocs;
+    int32_t *d_lens = nullptr, *d_pi = nullptr, *d_pj = nullptr;
+    int64_t *d_row_off = nullptr, *d_tr_row_off = nullptr, *d_stage_off = nullptr;
+    int32_t* d_tr_row_ptr = nullptr;
+    int32_t* d_tr_col = nullptr;
+    float* d_tr_val = nullptr;
+    int32_t* d_stage_col = nullptr;
+    float* d_stage_val = nullptr;
+    // two output sets: pass q writes set q % 2
+    int32_t* d_out_row_ptr[2] = {};
+    int64_t* d_out_nnz[2] = {};
+    int32_t* d_out_col[2] = {};
+    float* d_out_val[2] = {};
+    int64_t* d_scan_tmp = nullptr;
+    int* d_flags = nullptr;
+    hipStream_t last_stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool ran = false;
+    int last_set = 0;
+    int64_t last_nnz = 0;
+};
+
+namespace {
+
+qp_status relax_alloc(qp_relax* r, void** p, int64_t bytes) {
+    bytes = std::max<int64_t>(bytes, 4);
+    hipError_t e = hipMalloc(p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return qp::fail_msg(QP_ENOMEM, "hipMalloc of %lld bytes for the relaxation failed: %s", (long long)bytes,
+                            hipGetErrorString(e));
+    }
+    r->allocs.push_back(*p);
+    return QP_OK;
+}
+
+void relax_free(qp_relax* r) {
+    if (r->ran && r->done) hipEventSynchronize(r->done);
+    for (void* p : r->allocs) hipFree(p);
+    r->allocs.clear();
+    if (r->done) hipEventDestroy(r->done);
+    r->done = nullptr;
+}
+
+#define RX_TRY(expr)                                                                                       \
+    do {                                                                                                   \
+        hipError_t _e = (expr);                                                                            \
+        if (_e != hipSuccess) return qp::fail_msg(QP_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+qp_status qp_relax_create(const int32_t* lens, int32_t n, int64_t in_capacity, int32_t tree_threshold,
+                          double amplification, int32_t passes, float thresh, qp_relax** out) {
+    if (!out) return qp::fail_msg(QP_EINVAL, "out is NULL");
+    *out = nullptr;
+    qp_status st = qp::validate_lens(lens, n);
+    if (st != QP_OK) return st;
+    if (n > kMaxRelaxSeqs) return qp::fail_msg(QP_EINVAL, "n = %d sequences: at most %d", n, kMaxRelaxSeqs);
+    if (tree_threshold < 0) return qp::fail_msg(QP_EINVAL, "tree_threshold = %d < 0", tree_threshold);
+    if (!(amplification >= 1.0) || !std::isfinite(amplification))
+        return qp::fail_msg(QP_EINVAL, "amplification = %g is not >= 1", amplification);
+    if (passes < 1 || passes > 8) return qp::fail_msg(QP_EINVAL, "passes = %d is not in [1, 8]", passes);
+    if (!(thresh > 0.0f && thresh <= 1.0f)) return qp::fail_msg(QP_EINVAL, "thresh = %g is not in (0, 1]", (double)thresh);
+    if (in_capacity < 0) return qp::fail_msg(QP_EINVAL, "in_capacity = %lld < 0", (long long)in_capacity);
+    int dev = 0, n_cu = 0;
+    if ((st = qp::check_device(&dev, &n_cu)) != QP_OK) return st;
+    qp_relax* r = new (std::nothrow) qp_relax();
+    if (!r) return qp::fail_msg(QP_ENOMEM, "out of host memory");
+    r->device = dev;
+    r->n_cu = n_cu;
+    r->k = n;
+    r->P = (int64_t)n * (n - 1) / 2;
+    r->T = tree_threshold;
+    r->h = amplification;
+    r->passes = passes;
+    r->thresh = thresh;
+    r->cap = (int32_t)std::min<double>(qp::kMaxSeqLen, std::floor(1.0 / (double)thresh) + 1.0);
+    r->lens.assign(lens, lens + n);
+    const int64_t P = r->P;
+    std::vector<int32_t> pi((size_t)std::max<int64_t>(P, 1)), pj((size_t)std::max<int64_t>(P, 1));
+    std::vector<int64_t> row_off((size_t)P + 1), tr_off((size_t)P + 1), stage_off((size_t)P + 1);
+    {
+        int64_t q = 0, ro = 0, to = 0, so = 0;
+        for (int32_t i = 0; i + 1 < n; ++i)
+            for (int32_t j = i + 1; j < n; ++j, ++q) {
+                pi[q] = i;
+                pj[q] = j;
+                row_off[q] = ro;
+                tr_off[q] = to;
+                stage_off[q] = so;
+                ro += lens[i] + 1;
+                to += lens[j] + 1;
+                so += (int64_t)lens[i] * qp::row_bound(lens[j], thresh);
+            }
+        row_off[P] = ro;
+        tr_off[P] = to;
+        stage_off[P] = so;
+        r->total_rows = ro;
+        r->tr_rows = to;
+        r->bound = std::max<int64_t>(so, 1);
+    }
+    // the input holds at most its own bound; a caller may give the exact count
+    r->in_cap = in_capacity > 0 ? in_capacity : r->bound;
+    qp_status as = QP_OK;
+    auto A = [&](void** p, int64_t b) {
+        if (as == QP_OK) as = relax_alloc(r, p, b);
+    };
+    A((void**)&r->d_lens, 4LL * n);
+    A((void**)&r->d_pi, 4 * P);
+    A((void**)&r->d_pj, 4 * P);
+    A((void**)&r->d_row_off, 8 * (P + 1));
+    A((void**)&r->d_tr_row_off, 8 * (P + 1));
+    A((void**)&r->d_stage_off, 8 * (P + 1));
+    A((void**)&r->d_tr_row_ptr, 4 * r->tr_rows);
+    // transposed copies hold the input of a pass: the caller's first input,
+    // then (second pass on) a relaxed output, which stays within the bound
+    const int64_t tr_cap = passes > 1 ? std::max(r->in_cap, r->bound) : r->in_cap;
+    A((void**)&r->d_tr_col, 4 * tr_cap);
+    A((void**)&r->d_tr_val, 4 * tr_cap);
+    A((void**)&r->d_stage_col, 4 * r->bound);
+    A((void**)&r->d_stage_val, 4 * r->bound);
+    for (int q = 0; q < (passes > 1 ? 2 : 1); ++q) {
+        A((void**)&r->d_out_row_ptr[q], 4 * r->total_rows);
+        A((void**)&r->d_out_nnz[q], 8 * (P + 1));
+        A((void**)&r->d_out_col[q], 4 * r->bound);
+        A((void**)&r->d_out_val[q], 4 * r->bound);
+    }
+    A((void**)&r->d_scan_tmp, 8 * (qp::scan_tmp_elems(P + 1) + 8));
+    A((void**)&r->d_flags, 64);
+    if (as != QP_OK) {
+        relax_free(r);
+        delete r;
+        return as;
+    }
+    hipError_t e = hipMemcpy(r->d_lens, lens, 4ull * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && P > 0) e = hipMemcpy(r->d_pi, pi.data(), 4ull * P, hipMemcpyHostToDevice);
+    if (e == hipSuccess && P > 0) e = hipMemcpy(r->d_pj, pj.data(), 4ull * P, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_row_off, row_off.data(), 8ull * (P + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_tr_row_off, tr_off.data(), 8ull * (P + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_stage_off, stage_off.data(), 8ull * (P + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        relax_free(r);
+        delete r;
+        return qp::fail_msg(QP_EDEVICE, "relaxation set-up failed: %s", hipGetErrorString(e));
+    }
+    *out = r;
+    return QP_OK;
+}
+
+qp_status qp_relax_run(qp_relax* r, const qp_device_result* in, int64_t in_nnz, const int32_t* d_tdist,
+                       void* stream) {
+    if (!r) return qp::fail_msg(QP_EINVAL, "relax is NULL");
+    if (!in) return qp::fail_msg(QP_EINVAL, "in is NULL");
+    if (in->n_pairs != r->P)
+        return qp::fail_msg(QP_EINVAL, "input holds %lld pairs, the family %lld", (long long)in->n_pairs,
+                            (long long)r->P);
+    if (in->total_rows != r->total_rows)
+        return qp::fail_msg(QP_EINVAL, "input holds %lld row pointers, the family %lld", (long long)in->total_rows,
+                            (long long)r->total_rows);
+    if (in_nnz < 0 || in_nnz > r->in_cap)
+        return qp::fail_msg(QP_EINVAL, "input holds %lld entries, more than the %lld this relaxation was made for",
+                            (long long)in_nnz, (long long)r->in_cap);
+    if (r->P > 0 && (!in->row_off || !in->row_ptr || !in->nnz_off || !in->col || !in->val || !d_tdist))
+        return qp::fail_msg(QP_EINVAL, "a device input array is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RX_TRY(hipSetDevice(r->device));
+    if (r->ran) RX_TRY(hipEventSynchronize(r->done));  // one run at a time per relaxation
+    r->last_stream = s;
+    r->ran = true;
+    r->last_set = 0;
+    if (r->P == 0) {
+        RX_TRY(hipEventRecord(r->done, s));
+        return QP_OK;
+    }
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, r->d_flags, 16);
+    RX_TRY(hipGetLastError());
+    const int64_t waves_wanted = (r->P + kRelaxWaves - 1) / kRelaxWaves;
+    const unsigned grid = (unsigned)std::min<int64_t>(waves_wanted, (int64_t)r->n_cu * 8);
+    Csr cur{in->row_off, in->row_ptr, in->nnz_off, in->col, in->val};
+    for (int pass = 0; pass < r->passes; ++pass) {
+        const int q = pass & 1;
+        hipLaunchKernelGGL(k_transpose, dim3(grid), dim3(kWave * kRelaxWaves), 0, s, r->k, r->P, r->d_lens, r->d_pi,
+                           r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col, r->d_tr_val, r->d_flags);
+        RX_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_relax, dim3(grid), dim3(kWave * kRelaxWaves), 0, s, r->k, r->P, r->d_lens, r->d_pi,
+                           r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col, r->d_tr_val, d_tdist, r->T,
+                           (float)r->h, r->thresh, r->cap, r->d_row_off, r->d_out_row_ptr[q], r->d_stage_off,
+                           r->d_stage_col, r->d_stage_val, r->d_out_nnz[q], r->d_flags);
+        RX_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(r->d_out_nnz[q] + r->P), 2);
+        RX_TRY(hipGetLastError());
+        RX_TRY(qp::scan_i64(r->d_out_nnz[q], r->P + 1, r->d_scan_tmp, s));
+        RX_TRY(qp::launch_gather(r->P, r->d_out_nnz[q], r->d_stage_off, r->d_stage_col, r->d_stage_val,
+                                 r->d_out_col[q], r->d_out_val[q], r->bound, s));
+        cur = Csr{r->d_row_off, r->d_out_row_ptr[q], r->d_out_nnz[q], r->d_out_col[q], r->d_out_val[q]};
+        r->last_set = q;
+    }
+    RX_TRY(hipEventRecord(r->done, s));
+    return QP_OK;
+}
+
+qp_status qp_relax_sync(qp_relax* r, qp_device_result* out) {
+    if (!r) return qp::fail_msg(QP_EINVAL, "relax is NULL");
+    if (!r->ran) return qp::fail_msg(QP_EINVAL, "relaxation has not been run");
+    RX_TRY(hipSetDevice(r->device));
+    RX_TRY(hipEventSynchronize(r->done));
+    int64_t nnz = 0;
+    int flags = 0;
+    if (r->P > 0) {
+        RX_TRY(hipMemcpy(&nnz, r->d_out_nnz[r->last_set] + r->P, 8, hipMemcpyDeviceToHost));
+        RX_TRY(hipMemcpy(&flags, r->d_flags, 4, hipMemcpyDeviceToHost));
+    }
+    r->last_nnz = nnz;
+    if (flags & 4) return qp::fail_msg(QP_EINVAL, "an input entry's column lies outside its pair's second sequence");
+    if (flags & 2) return qp::fail_msg(QP_EDEVICE, "a relaxed row held more entries than its slots");
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->n_pairs = r->P;
+        out->total_rows = r->total_rows;
+        out->nnz = nnz;
+        out->pair_i = r->d_pi;
+        out->pair_j = r->d_pj;
+        out->row_off = r->d_row_off;
+        out->row_ptr = r->d_out_row_ptr[r->last_set];
+        out->nnz_off = r->d_out_nnz[r->last_set];
+        out->col = r->d_out_col[r->last_set];
+        out->val = r->d_out_val[r->last_set];
+    }
+    return QP_OK;
+}
+
+qp_status qp_relax_download(qp_relax* r, qp_result** out) {
+    if (!out) return qp::fail_msg(QP_EINVAL, "out is NULL");
+    *out = nullptr;
+    qp_device_result d;
+    qp_status st = qp_relax_sync(r, &d);
+    if (st != QP_OK) return st;
+    qp_result* res = qp::result_alloc(r->k, r->P, r->total_rows, d.nnz);
+    if (!res) return qp::fail_msg(QP_ENOMEM, "out of host memory");
+    res->thresh = r->thresh;
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t b) {
+        if (e == hipSuccess && b) e = hipMemcpy(dst, src, b, hipMemcpyDeviceToHost);
+    };
+    if (r->P > 0) {
+        cp(res->pair_i, d.pair_i, 4 * r->P);
+        cp(res->pair_j, d.pair_j, 4 * r->P);
+        cp(res->row_off, d.row_off, 8 * (r->P + 1));
+        cp(res->row_ptr, d.row_ptr, 4 * r->total_rows);
+        cp(res->nnz_off, d.nnz_off, 8 * (r->P + 1));
+        cp(res->col, d.col, 4 * d.nnz);
+        cp(res->val, d.val, 4 * d.nnz);
+    }
+    if (e != hipSuccess) {
+        qp_result_free(res);
+        return qp::fail_msg(QP_EDEVICE, "device-to-host copy failed: %s", hipGetErrorString(e));
+    }
+    *out = res;
+    return QP_OK;
+}
+
+int64_t qp_relax_device_bytes(const qp_relax* r) {
+    if (!r) return 0;
+    int64_t b = 0;
+    const int64_t P = r->P;
+    const int64_t tr_cap = r->passes > 1 ? std::max(r->in_cap, r->bound) : r->in_cap;
+    b += 4 * (int64_t)r->k + 8 * P + 24 * (P + 1) + 4 * r->tr_rows + 8 * tr_cap + 8 * r->bound;
+    b += (r->passes > 1 ? 2 : 1) * (4 * r->total_rows + 8 * (P + 1) + 8 * r->bound);
+    return b;
+}
+
+void qp_relax_destroy(qp_relax* r) {
+    if (!r) return;
+    hipSetDevice(r->device);
+    relax_free(r);
+    delete r;
+}
+
+}  // extern "C"

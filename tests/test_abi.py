@@ -215,3 +215,19 @@ def test_noalloc_validation_before_device(B, params):
         with pytest.raises(B.QpError) as e:
             B.posteriors_noalloc(4096, 4096, lens, p, 0.01, ptrs, bound, 0)
         assert e.value.status == B.QP_EDEVICE
+
+
+def test_relax_validation_before_device(B):
+    """qp_relax_create checks its arguments before any device call."""
+    lens = [50, 60, 70]
+    for args in ((-1, 3.0, 1, 0.01), (200, 0.5, 1, 0.01), (200, 3.0, 0, 0.01), (200, 3.0, 9, 0.01),
+                 (200, 3.0, 1, 0.0), (200, float("nan"), 1, 0.01)):
+        with pytest.raises(B.QpError) as e:
+            B.Relax(lens, *args)
+        assert e.value.status == B.QP_EINVAL
+    with pytest.raises(B.QpError) as e:
+        B.Relax([50, 0], 200, 3.0, 1, 0.01)
+    assert e.value.status == B.QP_EINVAL
+    with pytest.raises(B.QpError) as e:
+        B.Relax([50] * 2049, 200, 3.0, 1, 0.01)
+    assert e.value.status == B.QP_EINVAL and "2048" in str(e.value)
