@@ -50,7 +50,7 @@ def kernel_name(cls: int, fp64: bool, ck: bool = False) -> str:
     it (ck: the checkpointed FP32 form)."""
     r = cls + 1 if cls < 8 else 8
     if ck and not fp64:
-        return "qp::k_pairs_ck<%d, %s>" % (r, "true" if cls == 8 else "false")
+        return "qp::k_pairs_ck<%d, %s>" % (4 if cls == 8 else r, "true" if cls == 8 else "false")
     return "qp::k_pairs<%d, %s, %s>" % (r, "double" if fp64 else "float", "true" if cls == 8 else "false")
 
 
@@ -264,7 +264,7 @@ def main():
     from paper_1512_07437_amd import workload as W
 
     if args.recompute != "table":
-        B.set_tuning(recompute=[1 if args.recompute == "all" else 0] * 9)
+        B.set_tuning(recompute=[1, 1, 1, 1, 1, 0, 0, 0, 1] if args.recompute == "all" else [0] * 9)
     say("pair-kernel forms (1 = checkpointed) per class: %s" % B.get_tuning()["recompute"])
     if args.workload == "c4":
         out = serve_stream(args, say, args.families)

@@ -296,10 +296,11 @@ qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
  * writing every cell's forward values to device memory and reading them
  * back (recompute[c] = 0); same outputs, different memory / arithmetic
  * balance.  The checkpointed form exists for classes 0..4 (1 to 5 rows per
- * lane; QP_EINVAL for recompute[c] = 1 beyond), and the FP64 path always
- * uses the other form.
+ * lane) and for the banded class, which it runs in bands of 256 rows (4 per
+ * lane) instead of 512 (QP_EINVAL for recompute[c] = 1 on classes 5..7);
+ * the FP64 path always uses the other form.
  * Default: rows_per_lane[r-1] = r, waves_frac = 1, recompute = 1 for the
- * classes of 3 to 5 rows per lane.  Filled in by the project's autotuner
+ * classes of 3 to 5 rows per lane (the banded class is faster spilling).  Filled in by the project's autotuner
  * (paper_1512_07437_amd/autotune.py) from measurements per length bucket.
  */
 typedef struct {

@@ -769,11 +769,11 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     for (int c = 0; c < qp::kClasses; ++c) {
         qp_plan::ClassPlan& cp = pl->cls[c];
         if (cp.pairs == 0) continue;
-        cp.R = qp::class_rows_per_lane(c);
+        cp.ck = !pl->fp64 && pl->recompute[c] != 0;
+        cp.R = qp::class_rows(c, cp.ck);
         const int H = qp::kWave * cp.R;
         cp.nb_max = c == qp::kRMax ? (cp.mmax + H - 1) / H : 1;
         cp.cap = (int)std::max(1.0, std::min((double)cp.nmax, inv + 1.0));
-        cp.ck = !pl->fp64 && pl->recompute[c] != 0;
         size_slot(pl, &cp);
         const int per_cu = cp.ck ? qp::pairs_ck_blocks_per_cu(c) : qp::pairs_blocks_per_cu(c, pl->fp64);
         int64_t grid = std::max<int64_t>(1, (int64_t)std::llround(per_cu * n_cu * pl->waves_frac[c]));
@@ -1083,9 +1083,9 @@ qp_status qp_set_tuning(const qp_tuning* t) {
         for (int c = 0; c < 9; ++c) {
             if (t->recompute[c] != 0 && t->recompute[c] != 1)
                 return fail(QP_EINVAL, "recompute[%d] = %d is not 0 or 1", c, t->recompute[c]);
-            if (t->recompute[c] && c > qp::kCkMaxClass)
-                return fail(QP_EINVAL, "recompute[%d] = 1: the checkpointed form exists for classes 0..%d only", c,
-                            qp::kCkMaxClass);
+            if (t->recompute[c] && c > qp::kCkMaxClass && c != qp::kRMax)
+                return fail(QP_EINVAL, "recompute[%d] = 1: the checkpointed form exists for classes 0..%d and %d only",
+                            c, qp::kCkMaxClass, qp::kRMax);
         }
         for (int r = 0; r < 8; ++r)
             if (t->rows_per_lane[r] < r + 1 || t->rows_per_lane[r] > 8)
@@ -1207,7 +1207,7 @@ qp_status qp_plan_class_timing(qp_plan* pl, int32_t cls, double* kernel_ms, int6
     const qp_plan::ClassPlan& cp = pl->cls[cls];
     if (pairs) *pairs = cp.grid > 0 ? cp.pairs : 0;
     if (cells) *cells = cp.grid > 0 ? cp.cells : 0;
-    if (rows_per_lane) *rows_per_lane = qp::class_rows_per_lane(cls);
+    if (rows_per_lane) *rows_per_lane = cp.grid > 0 ? cp.R : qp::class_rows_per_lane(cls);
     if (kernel_ms) {
         *kernel_ms = 0.0;
         if (cp.grid > 0 && pl->ran) {

@@ -789,6 +789,12 @@ __global__ __launch_bounds__(kWave) void k_pair_one(PairArgs a, int64_t p) {
 //
 // The backward sweep's rescale closes every block (instead of every eighth
 // backward step), and its per-step work reads no memory.
+// band position of a routine: 0 / 1 fixed at compile time (single-band
+// kernels), 2 given at run time (the banded kernel keeps one instance of
+// each routine instead of one per top / middle / bottom band)
+constexpr int kBandRuntime = 2;
+__device__ __forceinline__ bool band_is(int mode, bool rt) { return mode == kBandRuntime ? rt : mode == 1; }
+
 template <int R> struct FwdSt {
     float W1[R], W2[R], D[R], gW[R], gD[R];
     float oM, oU1, oU2, ogM, ogU, aD, gaD, tv1, tv2, tgv;
@@ -806,10 +812,12 @@ constexpr int kYPad = kWave;
 constexpr int kYStride = kMaxSeqLen + 2 * kYPad;
 
 // state after column 0 of a band (before step 0)
-template <int R, bool FIRST, bool LAST>
+template <int R, int FM, int LM>
 __device__ __forceinline__ void ck_init(FwdSt<R>& f, int lane, bool used, int r0, int rows, int L,
                                         const Coef<float>& k, const Col0* __restrict__ col0,
-                                        const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout) {
+                                        const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout,
+                                        bool rt_first, bool rt_last) {
+    const bool FIRST = band_is(FM, rt_first), LAST = band_is(LM, rt_last);
     Col0 c0[R];
     int EH = INT_MIN, EP = INT_MIN;
 #pragma unroll
@@ -868,11 +876,13 @@ __device__ __forceinline__ void ck_init(FwdSt<R>& f, int lane, bool used, int r0
 // sm; WB: also write the band's boundary record (first sweep only)
 // (ycn: the residue of this step's column, read one step ahead; the read
 // for the next step is issued here)
-template <int R, bool FIRST, bool LAST, bool WB>
+template <int R, int FM, int LM, bool WB>
 __device__ __forceinline__ void ck_fstep(FwdSt<R>& f, float2 (&sm)[R], const int s, const int lane, const bool used,
                                          const int n, const int L, const int (&xo)[R], const uint8_t* ys,
                                          int& ycn, const float2* tab, const Coef<float>& k,
-                                         const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout) {
+                                         const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout,
+                                         bool rt_first, bool rt_last) {
+    const bool FIRST = band_is(FM, rt_first), LAST = band_is(LM, rt_last);
     const int j = s - lane + 1;
     const bool active = used && j >= 1 && j <= n;
     const int yc = ycn;
@@ -970,8 +980,9 @@ __device__ __forceinline__ void ck_put(float* ck, int w, int lane, float v) {
 __device__ __forceinline__ float ck_get(const float* ck, int w, int lane) {
     return __builtin_nontemporal_load(ck + w * kWave + lane);
 }
-template <int R, bool FIRST>
-__device__ __forceinline__ void ck_save(const FwdSt<R>& f, float* ck, int lane) {
+template <int R, int FM>
+__device__ __forceinline__ void ck_save(const FwdSt<R>& f, float* ck, int lane, bool rt_first) {
+    const bool FIRST = band_is(FM, rt_first);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         ck_put(ck, r, lane, f.W1[r]);
@@ -996,8 +1007,9 @@ __device__ __forceinline__ void ck_save(const FwdSt<R>& f, float* ck, int lane) 
     ck_put(ck, b + 10, lane, __int_as_float(f.EH));
     ck_put(ck, b + 11, lane, __int_as_float(f.EP));
 }
-template <int R, bool FIRST>
-__device__ __forceinline__ void ck_load(FwdSt<R>& f, const float* ck, int lane) {
+template <int R, int FM>
+__device__ __forceinline__ void ck_load(FwdSt<R>& f, const float* ck, int lane, bool rt_first) {
+    const bool FIRST = band_is(FM, rt_first);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         f.W1[r] = ck_get(ck, r, lane);
@@ -1027,12 +1039,13 @@ __device__ __forceinline__ void ck_load(FwdSt<R>& f, const float* ck, int lane) 
 
 // first sweep of one band: the state at every block start goes to ck, the
 // boundary records of a band above the last to fout; Z from the last band
-template <int R, bool FIRST, bool LAST>
+template <int R, int FM, int LM>
 __device__ void ck_fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* ys, int n, int r0,
                             int rows, int L, const float2* tab, const Coef<float>& k,
                             const Col0* __restrict__ col0, float* __restrict__ ck,
                             const FwdBnd<float>* __restrict__ fin, FwdBnd<float>* __restrict__ fout, float& zH,
-                            float& zP, int& ezH, int& ezP) {
+                            float& zP, int& ezH, int& ezP, bool rt_first, bool rt_last) {
+    const bool LAST = band_is(LM, rt_last);
     const bool used = lane < L;
     int xo[R];
 #pragma unroll
@@ -1041,20 +1054,21 @@ __device__ void ck_fwd_band(int lane, const uint8_t* __restrict__ x, const uint8
         xo[r] = (used && row < rows ? (int)x[r0 + row] : kPadCode) * kTabW;
     }
     FwdSt<R> f;
-    ck_init<R, FIRST, LAST>(f, lane, used, r0, rows, L, k, col0, fin, fout);
+    ck_init<R, FM, LM>(f, lane, used, r0, rows, L, k, col0, fin, fout, rt_first, rt_last);
     const int S = n + L - 1;
     float2 sm[R];
     int ycn = ys[-lane];
     for (int s0 = 0, blk = 0; s0 < S; s0 += kRescaleEvery, ++blk) {
-        ck_save<R, FIRST>(f, ck + (int64_t)blk * ck_words(R) * kWave, lane);
+        ck_save<R, FM>(f, ck + (int64_t)blk * ck_words(R) * kWave, lane, rt_first);
         if (s0 + kRescaleEvery <= S) {
 #pragma unroll
             for (int q = 0; q < kRescaleEvery; ++q)
-                ck_fstep<R, FIRST, LAST, true>(f, sm, s0 + q, lane, used, n, L, xo, ys, ycn, tab, k, fin, fout);
+                ck_fstep<R, FM, LM, true>(f, sm, s0 + q, lane, used, n, L, xo, ys, ycn, tab, k, fin, fout, rt_first,
+                                          rt_last);
             ck_frescale<R>(f);
         } else {
             for (int s = s0; s < S; ++s)
-                ck_fstep<R, FIRST, LAST, true>(f, sm, s, lane, used, n, L, xo, ys, ycn, tab, k, fin, fout);
+                ck_fstep<R, FM, LM, true>(f, sm, s, lane, used, n, L, xo, ys, ycn, tab, k, fin, fout, rt_first, rt_last);
         }
     }
     if (LAST) {
@@ -1072,13 +1086,15 @@ __device__ void ck_fwd_band(int lane, const uint8_t* __restrict__ x, const uint8
 
 // backward sweep of one band with the forward values recomputed per block
 // (a whole block of values held in registers)
-template <int R, bool FIRST, bool LAST>
+template <int R, int FM, int LM>
 __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* ys, int n, int r0,
                             int rows, int L, const float2* tab, const Coef<float>& k,
                             const float* __restrict__ ck, const FwdBnd<float>* __restrict__ fin,
                             const BwdBnd<float>* __restrict__ bin, BwdBnd<float>* __restrict__ bout, float invZH,
                             float invZP, int ezH, int ezP, float thresh, int cap, int4* __restrict__ hitlog,
-                            int& nlog, int32_t* __restrict__ rowcnt, int* __restrict__ flags, double& a11) {
+                            int& nlog, int32_t* __restrict__ rowcnt, int* __restrict__ flags, double& a11,
+                            bool rt_first, bool rt_last) {
+    const bool FIRST = band_is(FM, rt_first), LAST = band_is(LM, rt_last);
     const bool used = lane < L;
     int xo[R];
     bool inrow[R];
@@ -1245,15 +1261,15 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
         const int ns = FULL ? kRescaleEvery : min(kRescaleEvery, S - s0);
         FwdSt<R> f;
         int ycn = ys[s0 - lane];
-        ck_load<R, FIRST>(f, ck + (int64_t)blk * ck_words(R) * kWave, lane);
+        ck_load<R, FM>(f, ck + (int64_t)blk * ck_words(R) * kWave, lane, rt_first);
         if (!FIRST && lane == 0) f.bq = fin[min(s0 + 1, n)];
         const int2 ec = make_int2(f.EH, f.EP);
         float2 buf[kRescaleEvery][R];
 #pragma unroll
         for (int q = 0; q < kRescaleEvery; ++q)
             if (FULL || q < ns)
-                ck_fstep<R, FIRST, LAST, false>(f, buf[q], s0 + q, lane, used, n, L, xo, ys, ycn, tab, k, fin,
-                                                nullptr);
+                ck_fstep<R, FM, LM, false>(f, buf[q], s0 + q, lane, used, n, L, xo, ys, ycn, tab, k, fin,
+                                           nullptr, rt_first, rt_last);
 #pragma unroll
         for (int q = kRescaleEvery - 1; q >= 0; --q)
             if (FULL || q < ns) bstep(S - 1 - (s0 + q), buf[q], ec);
@@ -1314,13 +1330,10 @@ __device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, cha
         const FwdBnd<float>* fi = fb + (int64_t)(b > 0 ? b - 1 : 0) * a.bnd_stride;
         FwdBnd<float>* fo = fb + (int64_t)b * a.bnd_stride;
         if (!MULTI)
-            ck_fwd_band<R, true, true>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
-        else if (b == 0)
-            ck_fwd_band<R, true, false>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
-        else if (b == nb - 1)
-            ck_fwd_band<R, false, true>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
+            ck_fwd_band<R, 1, 1>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP, true, true);
         else
-            ck_fwd_band<R, false, false>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP, ezH, ezP);
+            ck_fwd_band<R, kBandRuntime, kBandRuntime>(lane, x, ys, n, r0, rows, L, tab, k, col0, c, fi, fo, zH, zP,
+                                                       ezH, ezP, b == 0, b == nb - 1);
         __threadfence_block();
     }
     const float invZH = (float)a.consts->w_hmm / zH;
@@ -1335,18 +1348,13 @@ __device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, cha
         const FwdBnd<float>* fi = fb + (int64_t)(b > 0 ? b - 1 : 0) * a.bnd_stride;
         const BwdBnd<float>* bi = bb + (int64_t)((b + 1) & 1) * a.bnd_stride;
         BwdBnd<float>* bo = bb + (int64_t)(b & 1) * a.bnd_stride;
-#define QP_CKB(F, Lb)                                                                                          \
-    ck_bwd_band<R, F, Lb>(lane, x, ys, n, r0, rows, L, tab, k, c, fi, bi, bo, invZH, invZP, ezH, ezP, a.thresh, \
-                          a.cap, hitlog, nlog, rp + 1, a.flags, a11)
         if (!MULTI)
-            QP_CKB(true, true);
-        else if (b == 0)
-            QP_CKB(true, false);
-        else if (b == nb - 1)
-            QP_CKB(false, true);
+            ck_bwd_band<R, 1, 1>(lane, x, ys, n, r0, rows, L, tab, k, c, fi, bi, bo, invZH, invZP, ezH, ezP, a.thresh,
+                                 a.cap, hitlog, nlog, rp + 1, a.flags, a11, true, true);
         else
-            QP_CKB(false, false);
-#undef QP_CKB
+            ck_bwd_band<R, kBandRuntime, kBandRuntime>(lane, x, ys, n, r0, rows, L, tab, k, c, fi, bi, bo, invZH,
+                                                       invZP, ezH, ezP, a.thresh, a.cap, hitlog, nlog, rp + 1,
+                                                       a.flags, a11, b == 0, b == nb - 1);
         __threadfence_block();
     }
     finish_pair(a, lane, p, m, n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
@@ -1765,6 +1773,7 @@ hipError_t launch_pairs_ck(int cls, int grid, const PairArgs& a, hipStream_t s) 
         case 2: return launch_pairs_ck_r<3, false>(grid, a, s);
         case 3: return launch_pairs_ck_r<4, false>(grid, a, s);
         case 4: return launch_pairs_ck_r<5, false>(grid, a, s);
+        case kRMax: return launch_pairs_ck_r<kCkBandRows, true>(grid, a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1782,6 +1791,7 @@ hipError_t launch_pair_one_ck(int cls, int64_t p, const PairArgs& a, hipStream_t
         case 2: return launch_pair_one_ck_r<3, false>(p, a, s);
         case 3: return launch_pair_one_ck_r<4, false>(p, a, s);
         case 4: return launch_pair_one_ck_r<5, false>(p, a, s);
+        case kRMax: return launch_pair_one_ck_r<kCkBandRows, true>(p, a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1801,6 +1811,7 @@ int pairs_ck_blocks_per_cu(int cls) {
         case 2: return blocks_per_cu_ck_r<3, false>();
         case 3: return blocks_per_cu_ck_r<4, false>();
         case 4: return blocks_per_cu_ck_r<5, false>();
+        case kRMax: return blocks_per_cu_ck_r<kCkBandRows, true>();
         default: return 1;
     }
 }

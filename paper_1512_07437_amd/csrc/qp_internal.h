@@ -123,7 +123,10 @@ int pairs_blocks_per_cu(int cls, int fp64);
 // the saved forward state of every block (ck_state_words(R) words per lane)
 // in place of the spilled values and exponents, and the forward boundary
 // records of every band
-constexpr int kCkMaxClass = 4;  // classes 0..4 (1..5 rows per lane) have the form
+constexpr int kCkMaxClass = 4;  // single-band classes 0..4 (1..5 rows per lane) have the form,
+constexpr int kCkBandRows = 4;  // and the banded class, in bands of 64 * 4 rows
+// rows per lane a class runs with in a given form
+inline int class_rows(int c, bool ck) { return ck && c == kRMax ? kCkBandRows : class_rows_per_lane(c); }
 hipError_t launch_pairs_ck(int cls, int grid, const PairArgs& a, hipStream_t s);
 hipError_t launch_pair_one_ck(int cls, int64_t p, const PairArgs& a, hipStream_t s);
 int pairs_ck_blocks_per_cu(int cls);

@@ -166,7 +166,7 @@ def test_tuning_table(B):
         B.set_tuning(recompute=[1, 0, 1, 1, 0, 0, 0, 0, 0])
         assert B.get_tuning()["recompute"] == [1, 0, 1, 1, 0, 0, 0, 0, 0]
         t = B.get_tuning()
-        for bad in ([2] + [0] * 8, [0] * 5 + [1] + [0] * 3, [0] * 8 + [1]):
+        for bad in ([2] + [0] * 8, [0] * 5 + [1] + [0] * 3, [0] * 7 + [1, 0]):
             with pytest.raises(B.QpError) as e:
                 B.set_tuning(recompute=bad)
             assert e.value.status == B.QP_EINVAL and B.get_tuning() == t

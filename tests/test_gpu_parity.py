@@ -433,15 +433,16 @@ _CK_OFF = pytest.mark.skip(reason="the checkpointed form for 6+ rows per lane co
 
 
 @pytest.mark.parametrize("R", [1, 2, 3, 4, 5, pytest.param(6, marks=_CK_OFF), pytest.param(7, marks=_CK_OFF),
-                               pytest.param(8, marks=_CK_OFF)])
+                               pytest.param(8, marks=_CK_OFF), 9])
 def test_recompute_form(B, params, R):
     """The checkpointed form (forward values recomputed per 8-step block in
     the backward sweep) against the spilling form and the oracle, on pairs
     whose row sequences need R rows per lane (partial blocks, lane edges and
-    a single-column pair included)."""
+    a single-column pair included); R = 9 stands for the banded class (rows
+    513..1536, bands of 256 rows in this form, 512 in the other)."""
     rng = np.random.default_rng(100 + R)
-    lo, hi = 64 * (R - 1) + 1, 64 * R
-    rows = [lo, hi, int(rng.integers(lo, hi + 1))]
+    lo, hi = (64 * (R - 1) + 1, 64 * R) if R <= 8 else (513, 1536)
+    rows = [lo, hi, int(rng.integers(lo, hi + 1))] if R <= 8 else [513, 768, 769, 1536]
     cols = [1, 7, 64 * R, int(rng.integers(50, 700)), int(rng.integers(50, 700))]
     fam = W.make_family(len(rows) + len(cols), rows + cols, 200 + R, r_sub=0.3, r_indel=0.05)
     pi = np.array([i for i in range(len(rows)) for _ in cols], dtype=np.int32)
@@ -450,7 +451,7 @@ def test_recompute_form(B, params, R):
     out = {}
     try:
         for form in (0, 1):
-            B.set_tuning(recompute=[form] * 5 + [0] * 4)
+            B.set_tuning(recompute=[form] * 5 + [0] * 3 + [form])
             out[form] = B.qp_posteriors_pairs(fam, pi, pj, B.make_params(params, 0), 0.01)
     finally:
         B.set_tuning(before["rows_per_lane"], before["waves_frac"], before["recompute"])
