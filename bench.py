@@ -48,10 +48,26 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_hbm_traffic.txt")
 def kernel_name(cls: int, fp64: bool, ck: bool = False) -> str:
     """Symbol of the persistent pair kernel of one class, as profilers print
     it (ck: the checkpointed FP32 form)."""
-    r = cls + 1 if cls < 8 else 8
+    banded = cls >= 8
+    r = cls + 1 if not banded else cls - 3
     if ck and not fp64:
-        return "qp::k_pairs_ck<%d, %s>" % (4 if cls == 8 else r, "true" if cls == 8 else "false")
-    return "qp::k_pairs<%d, %s, %s>" % (r, "double" if fp64 else "float", "true" if cls == 8 else "false")
+        return "qp::k_pairs_ck<%d, %s>" % (4 if banded else r, "true" if banded else "false")
+    return "qp::k_pairs<%d, %s, %s>" % (r, "double" if fp64 else "float", "true" if banded else "false")
+
+
+def class_kernels(B, plan, fp64: bool):
+    """Per-class rows (kernel, pairs, cells, average duration, TFLOP/s) of a
+    plan's timed runs."""
+    classes = []
+    for c in range(B.KERNEL_CLASSES):
+        c_ms, c_pairs, c_cells, c_r = plan.class_timing(c)
+        if c_pairs:
+            ck = bool(B.get_tuning()["recompute"][min(c, B.BANDED)])
+            classes.append({"class": c, "kernel": kernel_name(c, fp64, ck),
+                            "rows_per_lane": c_r, "pairs": c_pairs,
+                            "cells": c_cells, "avg_ms": round(c_ms, 4),
+                            "tflops": round(c_cells * FLOP_PER_CELL / (c_ms * 1e-3) / 1e12, 3) if c_ms > 0 else None})
+    return classes
 
 
 def committed_traffic(kernel: str, workload_key: str):
@@ -245,6 +261,11 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--classes", default="table", choices=["table", "serial", "concurrent"],
+                    help="kernel classes one after another on the run stream (serial) or side by side on "
+                         "forked streams (concurrent); default: the tuning table's choice")
+    ap.add_argument("--no-alone", action="store_true",
+                    help="skip the pass that times the dominant kernel with the device to itself")
     ap.add_argument("--recompute", default="table", choices=["table", "none", "all"],
                     help="FP32 pair-kernel form per class: the tuning table's choice, the spilling form for "
                          "every class (none) or the checkpointed form for every class (all)")
@@ -265,7 +286,10 @@ def main():
 
     if args.recompute != "table":
         B.set_tuning(recompute=[1, 1, 1, 1, 1, 0, 0, 0, 1] if args.recompute == "all" else [0] * 9)
-    say("pair-kernel forms (1 = checkpointed) per class: %s" % B.get_tuning()["recompute"])
+    if args.classes != "table":
+        B.set_tuning(concurrent_classes=int(args.classes == "concurrent"))
+    say("pair-kernel forms (1 = checkpointed) per class: %s; classes %s" % (
+        B.get_tuning()["recompute"], "concurrent" if B.get_tuning()["concurrent_classes"] else "one after another"))
     if args.workload == "c4":
         out = serve_stream(args, say, args.families)
         print(json.dumps(out), flush=True)
@@ -340,16 +364,10 @@ def main():
     # dominant one is the class with the most cells (the most algorithmic
     # work): a small class sharing the chip with a large one can have the
     # longer span without being what bounds the step
-    classes = []
-    for c in range(9):
-        c_ms, c_pairs, c_cells, c_r = plan.class_timing(c)
-        if c_pairs:
-            classes.append({"class": c, "kernel": kernel_name(c, fp64, bool(B.get_tuning()["recompute"][c])),
-                            "rows_per_lane": c_r, "pairs": c_pairs,
-                            "cells": c_cells, "avg_ms": round(c_ms, 4),
-                            "tflops": round(c_cells * FLOP_PER_CELL / (c_ms * 1e-3) / 1e12, 3) if c_ms > 0 else None})
+    classes = class_kernels(B, plan, fp64)
     dom = max(classes, key=lambda r: r["cells"]) if classes else None
     achieved = dom["tflops"] if dom else None
+    concurrent = bool(B.get_tuning()["concurrent_classes"])
     traffic = committed_traffic(dom["kernel"], args.workload + ("_fp64" if fp64 else "")) if dom else None
     out = {
         "metric": METRIC,
@@ -365,7 +383,8 @@ def main():
         "dtype": "fp32" if prec == 0 else "fp64",
         "data": "synthetic",
         "config": {"workload": desc, "pairs": n_pairs, "cells": cells, "thresh": args.thresh,
-                   "graph": not args.no_graph, "nnz": int(res["nnz"])},
+                   "graph": not args.no_graph, "nnz": int(res["nnz"]),
+                   "classes": "concurrent" if B.get_tuning()["concurrent_classes"] else "serial"},
         "pairs_per_s": round(n_pairs / (dt / args.steps), 1),
         "kernel_ms": round(kernel_ms, 4),
         "pipeline_ms": round(pipe_ms, 4),
@@ -427,6 +446,35 @@ def main():
             except Exception as e:  # the single-core figure above stands on its own
                 say("all-core cpu baseline skipped: %s" % e)
     plan.close()
+    if concurrent and dom and not args.no_alone:
+        # the classes share the device in the timed runs, so each kernel's
+        # duration there includes the time it yields to the others; one more
+        # plan runs them one after another (same pairs, same outputs) to give
+        # the dominant kernel's rate with the device to itself
+        B.set_tuning(concurrent_classes=0)
+        try:
+            alone_plan = B.Plan(lens, params, args.thresh, None if pairs is None else pairs[0],
+                                None if pairs is None else pairs[1], nnz_capacity=int(res["nnz"]) + 1024)
+            alone_plan.set_graph(not args.no_graph)
+            alone_plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+            alone_plan.sync()
+            alone_plan.timing(reset=True)
+            for _ in range(2):
+                alone_plan.run(d_seqs.data_ptr(), d_off.data_ptr(), sp)
+            alone_plan.sync()
+            a_kernel_ms, _, _ = alone_plan.timing()
+            alone = {r["kernel"]: r for r in class_kernels(B, alone_plan, fp64)}
+            alone_plan.close()
+        finally:
+            B.set_tuning(concurrent_classes=1)
+        a = alone.get(dom["kernel"])
+        if a and a["tflops"]:
+            out["roofline_alone"] = {"bound": "alu", "kernel": dom["kernel"], "achieved": a["tflops"], "peak": peak,
+                                     "unit": "TFLOP/s", "frac": round(a["tflops"] / peak, 4), "avg_ms": a["avg_ms"],
+                                     "what": "the same kernel with the device to itself: the plan's classes run "
+                                             "one after another, 2 runs after the timed region",
+                                     "classes_one_after_another_ms": round(a_kernel_ms, 4)}
+        say("dominant kernel alone: %s" % (out.get("roofline_alone"),))
     del res
     if args.workload == "c3" and args.c4_families > 0 and prec == B.QP_FP32_SCALED:
         # the metric's latency term: the C4 stream through the serving loop

@@ -259,14 +259,20 @@ qp_status qp_plan_download(qp_plan* plan, qp_result** out);
  * the run stream; *n_runs receives the number of runs averaged. */
 qp_status qp_plan_timing(qp_plan* plan, double* kernel_ms, double* pipeline_ms, int64_t* n_runs, int32_t reset);
 
-/* One kernel class of the plan (0..8): pairs whose row sequence needs
- * *rows_per_lane rows per lane of a 64-lane wavefront (classes 0..7: R =
- * 1..8, one band of 64R rows; class 8: R = 8 in several bands).  *pairs and
- * *cells are the pairs and m*n cells of this family in the class (0 when it
- * is absent); *kernel_ms is the average duration of the class's persistent
- * kernel over the timed runs (events recorded on the stream it runs on;
- * reset together with qp_plan_timing).  Any output pointer may be NULL.
- * QP_EINVAL for a class outside [0, 9). */
+/* Kernel classes of a plan: 0..7 run row sequences of at most 512 in one
+ * band of 64 R rows, R = 1..8 rows per lane of a 64-lane wavefront (the
+ * class of a pair set by the tuning table's rows_per_lane); 8..11 cut a
+ * longer row sequence into nb = ceil(m / 512) bands of 64 R rows with
+ * R = 5..8 = ceil(m / (64 nb)) (R = 4, bands of 256 rows, in the
+ * checkpointed form).  The tuning table's banded entry applies to all four. */
+#define QP_KERNEL_CLASSES 12
+
+/* One kernel class of the plan: pairs run with *rows_per_lane rows per lane.
+ * *pairs and *cells are the pairs and m*n cells of this family in the class
+ * (0 when it is absent); *kernel_ms is the average duration of the class's
+ * persistent kernel over the timed runs (events recorded on the stream it
+ * runs on; reset together with qp_plan_timing).  Any output pointer may be
+ * NULL.  QP_EINVAL for a class outside [0, QP_KERNEL_CLASSES). */
 qp_status qp_plan_class_timing(qp_plan* plan, int32_t cls, double* kernel_ms, int64_t* pairs, int64_t* cells,
                                int32_t* rows_per_lane);
 
@@ -284,29 +290,36 @@ qp_status qp_plan_set_graph(qp_plan* plan, int32_t use_graph);
 qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
 
 /*
- * Tuning table (process-wide; plans copy it when they are made).  The
- * posterior kernels come in classes by rows per lane R = 1..8 of a 64-lane
- * wavefront (class R-1), plus a banded class (8) for row sequences longer
- * than 512.  A pair whose row sequence needs at least r = ceil(m/64) rows
- * per lane runs with rows_per_lane[r-1] (r..8) rows per lane; every class
- * launches waves_frac[c] (0, 1] of its occupancy-limited persistent grid.
+ * Tuning table (process-wide; plans copy it when they are made).  Entries
+ * c = 0..7 are the single-band classes (R = c + 1 rows per lane of a 64-lane
+ * wavefront), entry 8 the banded classes 8..11 together (row sequences
+ * longer than 512).  A pair whose row sequence needs at least r = ceil(m/64)
+ * rows per lane runs with rows_per_lane[r-1] (r..8) rows per lane; every
+ * class launches waves_frac[c] (0, 1] of its occupancy-limited persistent
+ * grid.
  * recompute[c] = 1 runs class c's FP32 pairs in the checkpointed form: the
  * forward sweep keeps only its state every 8 steps and the backward sweep
  * recomputes each 8-step block's forward values in registers, instead of
  * writing every cell's forward values to device memory and reading them
  * back (recompute[c] = 0); same outputs, different memory / arithmetic
  * balance.  The checkpointed form exists for classes 0..4 (1 to 5 rows per
- * lane) and for the banded class, which it runs in bands of 256 rows (4 per
- * lane) instead of 512 (QP_EINVAL for recompute[c] = 1 on classes 5..7);
+ * lane) and for the banded classes, which it runs in bands of 256 rows (4
+ * per lane) (QP_EINVAL for recompute[c] = 1 on classes 5..7);
  * the FP64 path always uses the other form.
  * Default: rows_per_lane[r-1] = r, waves_frac = 1, recompute = 1 for the
- * classes of 3 to 5 rows per lane (the banded class is faster spilling).  Filled in by the project's autotuner
- * (paper_1512_07437_amd/autotune.py) from measurements per length bucket.
+ * classes of 3 to 5 rows per lane (the banded class is faster spilling).
+ * concurrent_classes = 1 runs a plan's kernel classes side by side on forked
+ * streams (one class's tail overlaps the next one's work); 0 runs them one
+ * after another on the run stream, largest rows per lane first, each with
+ * the whole device (and one workspace shared by all classes).  Default 1.
+ * Filled in by the project's autotuner (paper_1512_07437_amd/autotune.py)
+ * from measurements per length bucket.
  */
 typedef struct {
     int32_t rows_per_lane[8];
     double waves_frac[9];
     int32_t recompute[9];
+    int32_t concurrent_classes;
 } qp_tuning;
 
 /* Set the table (NULL restores the default); QP_EINVAL for a value out of

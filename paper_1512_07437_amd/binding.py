@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libqp.so")
 
 QP_OK, QP_EINVAL, QP_ENOMEM, QP_EDEVICE, QP_EBUSY, QP_ETIMEDOUT, QP_ECANCELED, QP_ENOSPC = 0, -1, -2, -3, -4, -5, -6, -7
 QP_FP32_SCALED, QP_FP64 = 0, 1
+KERNEL_CLASSES = 12  # QP_KERNEL_CLASSES: 0..7 single band, 8..11 banded (5..8 rows per lane)
+BANDED = 8           # tuning entry of the banded classes
 STATUS_NAMES = {0: "QP_OK", -1: "QP_EINVAL", -2: "QP_ENOMEM", -3: "QP_EDEVICE", -4: "QP_EBUSY",
                 -5: "QP_ETIMEDOUT", -6: "QP_ECANCELED", -7: "QP_ENOSPC"}
 
@@ -73,7 +75,7 @@ _P = ctypes.POINTER
 _u8pp = _P(_P(ctypes.c_uint8))
 class qp_tuning(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32 * 8), ("waves_frac", ctypes.c_double * 9),
-                ("recompute", ctypes.c_int32 * 9)]
+                ("recompute", ctypes.c_int32 * 9), ("concurrent_classes", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -157,11 +159,11 @@ TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_g
 
 
 def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Optional[Sequence[float]] = None,
-               recompute: Optional[Sequence[int]] = None):
+               recompute: Optional[Sequence[int]] = None, concurrent_classes: Optional[int] = None):
     """Process-wide tuning table for plans made afterwards (qp_set_tuning);
-    entries left None keep their current values; None for all three
+    entries left None keep their current values; None for all four
     restores the default."""
-    if rows_per_lane is None and waves_frac is None and recompute is None:
+    if rows_per_lane is None and waves_frac is None and recompute is None and concurrent_classes is None:
         _check(lib.qp_set_tuning(None))
         return
     t = get_tuning()
@@ -172,6 +174,7 @@ def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Option
     v.rows_per_lane[:] = [int(x) for x in r]
     v.waves_frac[:] = [float(x) for x in w]
     v.recompute[:] = [int(x) for x in c]
+    v.concurrent_classes = int(t["concurrent_classes"] if concurrent_classes is None else concurrent_classes)
     _check(lib.qp_set_tuning(ctypes.byref(v)))
 
 
@@ -179,7 +182,7 @@ def get_tuning() -> Dict[str, list]:
     t = qp_tuning()
     _check(lib.qp_get_tuning(ctypes.byref(t)))
     return {"rows_per_lane": list(t.rows_per_lane), "waves_frac": list(t.waves_frac),
-            "recompute": list(t.recompute)}
+            "recompute": list(t.recompute), "concurrent_classes": int(t.concurrent_classes)}
 
 
 def load_tuning(path: str = TUNING_PATH) -> bool:
@@ -189,7 +192,7 @@ def load_tuning(path: str = TUNING_PATH) -> bool:
         return False
     with open(path) as f:
         d = json.load(f)
-    set_tuning(d["rows_per_lane"], d["waves_frac"], d.get("recompute"))
+    set_tuning(d["rows_per_lane"], d["waves_frac"], d.get("recompute"), d.get("concurrent_classes"))
     return True
 
 

@@ -31,6 +31,7 @@ void default_tuning(qp_tuning* t) {
         t->waves_frac[c] = 1.0;
         t->recompute[c] = c >= 2 && c <= 4 ? 1 : 0;
     }
+    t->concurrent_classes = 1;
 }
 qp_tuning g_tuning = [] {
     qp_tuning t;
@@ -66,6 +67,7 @@ int64_t row_bound(int32_t c, float thresh) {
 
 constexpr int kNumEventSets = 8;
 // layout of the plan's int counters
+constexpr int kMaxSide = 3;                           // side streams of concurrent classes
 constexpr int kIntHeads = 0;                          // [kClasses] queue heads
 constexpr int kIntFlags = 12;                         // overflow flags
 constexpr int kIntHist = 16;                          // [kKeyBins]
@@ -155,8 +157,8 @@ struct qp_plan {
         char* d_scratch = nullptr;
     } cls[qp::kClasses];
     int n_side = 0;
-    hipStream_t side[3] = {};
-    hipEvent_t fork_ev = nullptr, join_ev[3] = {};
+    hipStream_t side[kMaxSide] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kMaxSide] = {};
     // marks the end of result copies enqueued on the run stream
     hipEvent_t copy_ev = nullptr;
     // device memory (one allocation each; freed in destroy)
@@ -297,8 +299,8 @@ void qp::current_tuning(qp::ClassMap* map, double* waves_frac, int* recompute) {
     std::lock_guard<std::mutex> g(g_tuning_mu);
     for (int r = 0; r < qp::kRMax; ++r) map->c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
     for (int c = 0; c < qp::kClasses; ++c) {
-        waves_frac[c] = g_tuning.waves_frac[c];
-        recompute[c] = g_tuning.recompute[c];
+        waves_frac[c] = g_tuning.waves_frac[qp::tune_index(c)];
+        recompute[c] = g_tuning.recompute[qp::tune_index(c)];
     }
 }
 void qp::slot_layout(int R, int mmax, int nmax, int nb_max, int cap, int fp64, bool ck, qp::PairArgs* a) {
@@ -361,6 +363,36 @@ static void set_class_args(qp_plan* pl) {
 
 // allocation of all plan buffers (needs pool_cap and grids); with `dry`
 // only adds up the bytes it would allocate
+// Streams of a plan's classes: with classes side by side, the present
+// classes from the largest down are dealt round-robin over min(present,
+// kMaxSide) side streams; one after another, they all share the run stream.
+// group[c] receives class c's stream, the return value the number of them.
+static int stream_groups(const qp_plan* pl, int* group) {
+    int np = 0;
+    for (int c = qp::kClasses - 1; c >= 0; --c) {
+        group[c] = 0;
+        if (pl->cls[c].grid > 0) group[c] = np++;
+    }
+    const int ns = pl->single_stream || np <= 1 ? 1 : std::min(np, kMaxSide);
+    for (int c = 0; c < qp::kClasses; ++c) group[c] %= ns;
+    return ns;
+}
+
+// scratch bytes of the plan's classes (one area per stream)
+static int64_t scratch_bytes(const qp_plan* pl, int* n_areas) {
+    int group[qp::kClasses];
+    int64_t most[kMaxSide] = {};
+    const int ng = stream_groups(pl, group);
+    for (int c = 0; c < qp::kClasses; ++c)
+        if (pl->cls[c].grid > 0)
+            most[group[c]] = std::max(most[group[c]], (int64_t)pl->cls[c].grid * qp::kWavesPerBlock *
+                                                          pl->cls[c].args.slot_bytes);
+    int64_t sum = 0;
+    for (int g = 0; g < ng; ++g) sum += most[g];
+    if (n_areas) *n_areas = ng;
+    return sum;
+}
+
 static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     const int64_t P = pl->P;
     qp_status st;
@@ -405,21 +437,20 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     ALLOC(pl->d_dist, P);
     ALLOC(pl->d_logz, 2 * P);
     ALLOC(pl->d_scan_tmp, qp::scan_tmp_elems(P + 1) + 8);
-    if (pl->single_stream) {
-        // classes run one after another: one scratch area serves them all
-        int64_t most = 0;
+    {
+        // classes that run one after another on one stream share a scratch
+        // area: one area per stream, as large as its largest class's
+        int group[qp::kClasses];
+        int64_t most[kMaxSide] = {};
+        const int ng = stream_groups(pl, group);
         for (int c = 0; c < qp::kClasses; ++c)
             if (pl->cls[c].grid > 0)
-                most = std::max(most, (int64_t)pl->cls[c].grid * qp::kWavesPerBlock * pl->cls[c].args.slot_bytes);
-        char* shared = nullptr;
-        ALLOC(shared, most);
+                most[group[c]] = std::max(most[group[c]], (int64_t)pl->cls[c].grid * qp::kWavesPerBlock *
+                                                              pl->cls[c].args.slot_bytes);
+        char* area[kMaxSide] = {};
+        for (int g = 0; g < ng; ++g) ALLOC(area[g], most[g]);
         for (int c = 0; c < qp::kClasses; ++c)
-            if (pl->cls[c].grid > 0) pl->cls[c].d_scratch = shared;
-    } else {
-        for (int c = 0; c < qp::kClasses; ++c)
-            if (pl->cls[c].grid > 0)
-                ALLOC(pl->cls[c].d_scratch,
-                      (int64_t)pl->cls[c].grid * qp::kWavesPerBlock * pl->cls[c].args.slot_bytes);
+            if (pl->cls[c].grid > 0) pl->cls[c].d_scratch = area[group[c]];
     }
 #undef ALLOC
     if (dry) return QP_OK;
@@ -712,9 +743,10 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
         std::lock_guard<std::mutex> g(g_tuning_mu);
         for (int r = 0; r < qp::kRMax; ++r) pl->cmap.c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
         for (int c = 0; c < qp::kClasses; ++c) {
-            pl->waves_frac[c] = g_tuning.waves_frac[c];
-            pl->recompute[c] = g_tuning.recompute[c];
+            pl->waves_frac[c] = g_tuning.waves_frac[qp::tune_index(c)];
+            pl->recompute[c] = g_tuning.recompute[qp::tune_index(c)];
         }
+        pl->single_stream = g_tuning.concurrent_classes == 0;
     }
     if (!all) {
         pl->list_i.assign(pair_i, pair_i + P);
@@ -765,22 +797,21 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     pl->pool_cap = nnz_capacity > 0    ? nnz_capacity
                    : nnz_capacity == -1 ? std::max<int64_t>(bound, 1)
                                         : std::max<int64_t>(est + 1024, 1024);
-    int64_t want_bytes = 0;
     for (int c = 0; c < qp::kClasses; ++c) {
         qp_plan::ClassPlan& cp = pl->cls[c];
         if (cp.pairs == 0) continue;
         cp.ck = !pl->fp64 && pl->recompute[c] != 0;
         cp.R = qp::class_rows(c, cp.ck);
         const int H = qp::kWave * cp.R;
-        cp.nb_max = c == qp::kRMax ? (cp.mmax + H - 1) / H : 1;
+        cp.nb_max = qp::class_banded(c) ? (cp.mmax + H - 1) / H : 1;
         cp.cap = (int)std::max(1.0, std::min((double)cp.nmax, inv + 1.0));
         size_slot(pl, &cp);
         const int per_cu = cp.ck ? qp::pairs_ck_blocks_per_cu(c) : qp::pairs_blocks_per_cu(c, pl->fp64);
         int64_t grid = std::max<int64_t>(1, (int64_t)std::llround(per_cu * n_cu * pl->waves_frac[c]));
         grid = std::min<int64_t>(grid, std::max<int64_t>(1, (cp.pairs + qp::kWavesPerBlock - 1) / qp::kWavesPerBlock));
         cp.grid = (int)grid;
-        want_bytes += grid * qp::kWavesPerBlock * cp.args.slot_bytes;
     }
+    const int64_t want_bytes = scratch_bytes(pl, nullptr);
     const int64_t budget = (int64_t)(free_b / 2);
     if (want_bytes > budget) {
         const double f = (double)budget / (double)want_bytes;
@@ -913,7 +944,7 @@ qp_status qp::plan_materialize(qp_plan* pl) {
     int n_present = 0;
     for (int c = 0; c < qp::kClasses; ++c) n_present += pl->cls[c].grid > 0;
     if (e == hipSuccess && n_present > 1 && !pl->single_stream) {
-        pl->n_side = std::min(n_present, 3);
+        pl->n_side = std::min(n_present, kMaxSide);
         e = hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming);
         for (int q = 0; q < pl->n_side && e == hipSuccess; ++q) {
             e = hipStreamCreateWithFlags(&pl->side[q], hipStreamNonBlocking);
@@ -1083,9 +1114,9 @@ qp_status qp_set_tuning(const qp_tuning* t) {
         for (int c = 0; c < 9; ++c) {
             if (t->recompute[c] != 0 && t->recompute[c] != 1)
                 return fail(QP_EINVAL, "recompute[%d] = %d is not 0 or 1", c, t->recompute[c]);
-            if (t->recompute[c] && c > qp::kCkMaxClass && c != qp::kRMax)
+            if (t->recompute[c] && c > qp::kCkMaxClass && c != qp::kBandClass)
                 return fail(QP_EINVAL, "recompute[%d] = 1: the checkpointed form exists for classes 0..%d and %d only",
-                            c, qp::kCkMaxClass, qp::kRMax);
+                            c, qp::kCkMaxClass, qp::kBandClass);
         }
         for (int r = 0; r < 8; ++r)
             if (t->rows_per_lane[r] < r + 1 || t->rows_per_lane[r] > 8)
@@ -1093,6 +1124,8 @@ qp_status qp_set_tuning(const qp_tuning* t) {
         for (int c = 0; c < 9; ++c)
             if (!(t->waves_frac[c] > 0.0 && t->waves_frac[c] <= 1.0))
                 return fail(QP_EINVAL, "waves_frac[%d] = %g is not in (0, 1]", c, t->waves_frac[c]);
+        if (t->concurrent_classes != 0 && t->concurrent_classes != 1)
+            return fail(QP_EINVAL, "concurrent_classes = %d is not 0 or 1", t->concurrent_classes);
         v = *t;
     }
     std::lock_guard<std::mutex> g(g_tuning_mu);
@@ -1244,7 +1277,7 @@ void qp_plan_destroy(qp_plan* pl) {
                 if (pl->cev[g][c][q]) hipEventDestroy(pl->cev[g][c][q]);
     }
     if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < kMaxSide; ++q) {
         if (pl->side[q]) hipStreamDestroy(pl->side[q]);
         if (pl->join_ev[q]) hipEventDestroy(pl->join_ev[q]);
     }

@@ -138,16 +138,23 @@ __device__ __forceinline__ int res_uniform(const uint8_t* y, int idx) {
     return (int)((w[idx >> 2] >> ((idx & 3) * 8)) & 0xffu);
 }
 
+// Band position modes of the band routines: 1 / 0 fix "top band" (or
+// "bottom band") at compile time, so single-band pairs carry no boundary
+// code; kBandRuntime takes it from a wave-uniform flag (scalar branches).
+constexpr int kBandRuntime = 2;
+__device__ __forceinline__ bool band_is(int mode, bool rt) { return mode == kBandRuntime ? rt : mode == 1; }
+
 // ---------------------------------------------------------------- forward
 // One band of rows [r0, r0+rows) of pair (x, y); L lanes carry R rows each.
-template <int R, typename T, bool first, bool last>
+template <int R, typename T, int FM, int LM>
 __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* __restrict__ y, int n, int r0,
                          int rows, int L, const typename Pair2<T>::type* tab,
                          const Coef<T>& k, const Col0* __restrict__ col0,
                          typename Pair2<T>::type* __restrict__ spill, int2* __restrict__ exps,
                          const FwdBnd<T>* __restrict__ fin, FwdBnd<T>* __restrict__ fout, T& zH, T& zP,
-                         int& ezH, int& ezP) {
+                         int& ezH, int& ezP, bool rt_first, bool rt_last) {
     using V2 = typename Pair2<T>::type;
+    const bool first = band_is(FM, rt_first), last = band_is(LM, rt_last);
     const bool used = lane < L;
     int xo[R];
 #pragma unroll
@@ -364,17 +371,18 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
 }
 
 // --------------------------------------------------------------- backward
-// FIRST / LAST: the band is the top / bottom band of the pair (compile time,
-// so single-band pairs carry no band-boundary code).
-template <int R, typename T, bool FIRST, bool LAST>
+// FIRST / LAST: the band is the top / bottom band of the pair (band position
+// modes as in the forward routine).
+template <int R, typename T, int FM, int LM>
 __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t* __restrict__ y, int n, int r0,
                          int rows, int L, const typename Pair2<T>::type* tab, const Coef<T>& k,
                          const typename Pair2<T>::type* __restrict__ spill, const int2* __restrict__ exps,
                          const BwdBnd<T>* __restrict__ bin, BwdBnd<T>* __restrict__ bout, T invZH, T invZP, int ezH,
                          int ezP, float thresh, int cap, int4* __restrict__ hitlog, int& nlog,
                          int32_t* __restrict__ rowcnt, int* __restrict__ flags,
-                         double& a11) {
+                         double& a11, bool rt_first, bool rt_last) {
     using V2 = typename Pair2<T>::type;
+    const bool FIRST = band_is(FM, rt_first), LAST = band_is(LM, rt_last);
     const bool used = lane < L;
     int xo[R];
 #pragma unroll
@@ -654,17 +662,14 @@ __device__ void finish_pair(const PairArgs& a, int lane, int64_t p, int m, int n
 }
 
 // ------------------------------------------------------------ one pair
-template <int R, typename T, bool MULTI>
-__device__ void process_pair(const PairArgs& a, int lane, char* slot, const typename Pair2<T>::type* tab,
-                             const Coef<T>& k, int64_t p) {
+// Forward sweep over the bands top to bottom, backward sweep bottom to top,
+// then the pair's output.  RB rows per lane, bands of kWave * RB rows.
+template <int RB, typename T, bool MULTI>
+__device__ __forceinline__ void pair_bands(const PairArgs& a, int lane, char* slot,
+                                           const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p, int m,
+                                           int n, const uint8_t* x, const uint8_t* y) {
     using V2 = typename Pair2<T>::type;
-    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
-    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
-    const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
-    const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
-    const uint8_t* x = a.seqs + uniform64(a.seq_off[pi]);
-    const uint8_t* y = a.seqs + uniform64(a.seq_off[pj]);
-    const int H = kWave * R;
+    const int H = kWave * RB;
     const int nb = MULTI ? (m + H - 1) / H : 1;
     V2* spill = reinterpret_cast<V2*>(slot);
     int2* exps = reinterpret_cast<int2*>(slot + a.off_exps);
@@ -679,19 +684,23 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
     for (int b = 0; b < nb; ++b) {
         const int r0 = b * H;
         const int rows = min(H, m - r0);
-        const int L = (rows + R - 1) / R;
+        const int L = (rows + RB - 1) / RB;
         V2* sp = spill + (int64_t)b * a.spill_band_stride;
         int2* ex = exps + (int64_t)b * a.exps_band_stride;
         const FwdBnd<T>* fi = fb + (int64_t)((b + 1) & 1) * a.bnd_stride;
         FwdBnd<T>* fo = fb + (int64_t)(b & 1) * a.bnd_stride;
+        // the top band's position is fixed at compile time (its lane 0
+        // starts from the begin state, the others from a boundary record:
+        // different live values), the bottom band's is a runtime flag
         if (!MULTI)
-            fwd_band<R, T, true, true>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
+            fwd_band<RB, T, 1, 1>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP, true,
+                                  true);
         else if (b == 0)
-            fwd_band<R, T, true, false>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
-        else if (b == nb - 1)
-            fwd_band<R, T, false, true>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
+            fwd_band<RB, T, 1, kBandRuntime>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH,
+                                             ezP, true, nb == 1);
         else
-            fwd_band<R, T, false, false>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH, ezP);
+            fwd_band<RB, T, 0, kBandRuntime>(lane, x, y, n, r0, rows, L, tab, k, col0, sp, ex, fi, fo, zH, zP, ezH,
+                                             ezP, false, b == nb - 1);
         __threadfence_block();
     }
     const T invZH = T(a.consts->w_hmm) / zH;
@@ -701,26 +710,37 @@ __device__ void process_pair(const PairArgs& a, int lane, char* slot, const type
     for (int b = nb - 1; b >= 0; --b) {
         const int r0 = b * H;
         const int rows = min(H, m - r0);
-        const int L = (rows + R - 1) / R;
+        const int L = (rows + RB - 1) / RB;
         const V2* sp = spill + (int64_t)b * a.spill_band_stride;
         const int2* ex = exps + (int64_t)b * a.exps_band_stride;
         const BwdBnd<T>* bi = bb + (int64_t)((b + 1) & 1) * a.bnd_stride;
         BwdBnd<T>* bo = bb + (int64_t)(b & 1) * a.bnd_stride;
-#define QP_BWD(F, Lb)                                                                                      \
-    bwd_band<R, T, F, Lb>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH, ezP, a.thresh, \
-                          a.cap, hitlog, nlog, rp + 1, a.flags, a11)
+        // here the bottom band's position is the compile-time one (the
+        // lane L-1 below it reads a boundary record or nothing)
         if (!MULTI)
-            QP_BWD(true, true);
-        else if (b == 0)
-            QP_BWD(true, false);
+            bwd_band<RB, T, 1, 1>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH, ezP,
+                                  a.thresh, a.cap, hitlog, nlog, rp + 1, a.flags, a11, true, true);
         else if (b == nb - 1)
-            QP_BWD(false, true);
+            bwd_band<RB, T, kBandRuntime, 1>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH,
+                                             ezP, a.thresh, a.cap, hitlog, nlog, rp + 1, a.flags, a11, b == 0, true);
         else
-            QP_BWD(false, false);
-#undef QP_BWD
+            bwd_band<RB, T, kBandRuntime, 0>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH,
+                                             ezP, a.thresh, a.cap, hitlog, nlog, rp + 1, a.flags, a11, b == 0, false);
         __threadfence_block();
     }
     finish_pair(a, lane, p, m, n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
+}
+
+template <int R, typename T, bool MULTI>
+__device__ __forceinline__ void process_pair(const PairArgs& a, int lane, char* slot,
+                                             const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p) {
+    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
+    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
+    const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
+    const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
+    const uint8_t* x = a.seqs + uniform64(a.seq_off[pi]);
+    const uint8_t* y = a.seqs + uniform64(a.seq_off[pj]);
+    pair_bands<R, T, MULTI>(a, lane, slot, tab, k, p, m, n, x, y);
 }
 
 // One persistent launch per kernel class: waves pop pairs of their class
@@ -792,8 +812,6 @@ __global__ __launch_bounds__(kWave) void k_pair_one(PairArgs a, int64_t p) {
 // band position of a routine: 0 / 1 fixed at compile time (single-band
 // kernels), 2 given at run time (the banded kernel keeps one instance of
 // each routine instead of one per top / middle / bottom band)
-constexpr int kBandRuntime = 2;
-__device__ __forceinline__ bool band_is(int mode, bool rt) { return mode == kBandRuntime ? rt : mode == 1; }
 
 template <int R> struct FwdSt {
     float W1[R], W2[R], D[R], gW[R], gD[R];
@@ -1728,6 +1746,9 @@ hipError_t launch_pairs(int cls, int fp64, int grid, const PairArgs& a, hipStrea
         case 5: return launch_pairs_r<6, false>(fp64, grid, a, s);
         case 6: return launch_pairs_r<7, false>(fp64, grid, a, s);
         case 7: return launch_pairs_r<8, false>(fp64, grid, a, s);
+        case kBandClass + 0: return launch_pairs_r<5, true>(fp64, grid, a, s);
+        case kBandClass + 1: return launch_pairs_r<6, true>(fp64, grid, a, s);
+        case kBandClass + 2: return launch_pairs_r<7, true>(fp64, grid, a, s);
         default: return launch_pairs_r<8, true>(fp64, grid, a, s);
     }
 }
@@ -1751,6 +1772,9 @@ hipError_t launch_pair_one(int cls, int fp64, int64_t p, const PairArgs& a, hipS
         case 5: return launch_pair_one_r<6, false>(fp64, p, a, s);
         case 6: return launch_pair_one_r<7, false>(fp64, p, a, s);
         case 7: return launch_pair_one_r<8, false>(fp64, p, a, s);
+        case kBandClass + 0: return launch_pair_one_r<5, true>(fp64, p, a, s);
+        case kBandClass + 1: return launch_pair_one_r<6, true>(fp64, p, a, s);
+        case kBandClass + 2: return launch_pair_one_r<7, true>(fp64, p, a, s);
         default: return launch_pair_one_r<8, true>(fp64, p, a, s);
     }
 }
@@ -1773,8 +1797,7 @@ hipError_t launch_pairs_ck(int cls, int grid, const PairArgs& a, hipStream_t s) 
         case 2: return launch_pairs_ck_r<3, false>(grid, a, s);
         case 3: return launch_pairs_ck_r<4, false>(grid, a, s);
         case 4: return launch_pairs_ck_r<5, false>(grid, a, s);
-        case kRMax: return launch_pairs_ck_r<kCkBandRows, true>(grid, a, s);
-        default: return hipErrorInvalidValue;
+        default: return class_banded(cls) ? launch_pairs_ck_r<kCkBandRows, true>(grid, a, s) : hipErrorInvalidValue;
     }
 }
 
@@ -1791,8 +1814,7 @@ hipError_t launch_pair_one_ck(int cls, int64_t p, const PairArgs& a, hipStream_t
         case 2: return launch_pair_one_ck_r<3, false>(p, a, s);
         case 3: return launch_pair_one_ck_r<4, false>(p, a, s);
         case 4: return launch_pair_one_ck_r<5, false>(p, a, s);
-        case kRMax: return launch_pair_one_ck_r<kCkBandRows, true>(p, a, s);
-        default: return hipErrorInvalidValue;
+        default: return class_banded(cls) ? launch_pair_one_ck_r<kCkBandRows, true>(p, a, s) : hipErrorInvalidValue;
     }
 }
 
@@ -1811,8 +1833,7 @@ int pairs_ck_blocks_per_cu(int cls) {
         case 2: return blocks_per_cu_ck_r<3, false>();
         case 3: return blocks_per_cu_ck_r<4, false>();
         case 4: return blocks_per_cu_ck_r<5, false>();
-        case kRMax: return blocks_per_cu_ck_r<kCkBandRows, true>();
-        default: return 1;
+        default: return class_banded(cls) ? blocks_per_cu_ck_r<kCkBandRows, true>() : 1;
     }
 }
 
@@ -1841,6 +1862,9 @@ int pairs_blocks_per_cu(int cls, int fp64) {
         case 5: return blocks_per_cu_r<6, false>(fp64);
         case 6: return blocks_per_cu_r<7, false>(fp64);
         case 7: return blocks_per_cu_r<8, false>(fp64);
+        case kBandClass + 0: return blocks_per_cu_r<5, true>(fp64);
+        case kBandClass + 1: return blocks_per_cu_r<6, true>(fp64);
+        case kBandClass + 2: return blocks_per_cu_r<7, true>(fp64);
         default: return blocks_per_cu_r<8, true>(fp64);
     }
 }

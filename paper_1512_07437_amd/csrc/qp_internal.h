@@ -20,21 +20,35 @@ constexpr int kMaxSeqLen = 1536;    // longest accepted sequence (QP_MAX_SEQ_LEN
 constexpr int kRescaleEvery = 8;    // steps between power-of-two rescales
 constexpr int kKeyBins = 1024;      // queue keys: kernel class x cost bin
 constexpr int kCostBins = 64;       // half-octave bins of m*n per kernel class
-constexpr int kClasses = 9;         // R = 1..8 single band, R = 8 banded
+constexpr int kBandClass = kRMax;   // first banded class
+constexpr int kBandRMin = 5;        // banded classes: 5..8 rows per lane
+constexpr int kClasses = kBandClass + kRMax - kBandRMin + 1;  // 8 single band + 4 banded
+constexpr int kTuneClasses = kBandClass + 1;  // tuning entries: 8 single band, one for all banded
+static_assert(kClasses * kCostBins <= kKeyBins, "queue keys");
 
 // Kernel class per minimal rows per lane: a pair whose row sequence needs
 // r = ceil(m/64) <= 8 rows per lane runs in class c[r-1] (R = c+1 >= r rows
-// per lane; the identity map uses the fewest); longer rows are cut into
-// bands of 64*8 and go to the banded class.  Chosen per length bucket by the
-// tuning table.
+// per lane; the identity map uses the fewest), chosen per length bucket by
+// the tuning table.  Longer rows are cut into nb = ceil(m / (64*8)) bands,
+// each of 64 R rows with the fewest rows per lane R that still needs only nb
+// bands (R = ceil(m / (64 nb)), 5..8 for m > 512): bands that fill their
+// lanes, one banded class per R.
 struct ClassMap {
     int8_t c[kRMax];
 };
+__host__ __device__ inline int banded_rows(int m) {
+    const int nb = (m + kWave * kRMax - 1) / (kWave * kRMax);
+    const int r = (m + kWave * nb - 1) / (kWave * nb);
+    return r < kBandRMin ? kBandRMin : (r > kRMax ? kRMax : r);
+}
 __host__ __device__ inline int pair_class(int m, const ClassMap& map) {
     const int R = (m + kWave - 1) / kWave;
-    return R <= kRMax ? map.c[R - 1] : kRMax;
+    return R <= kRMax ? map.c[R - 1] : kBandClass + banded_rows(m) - kBandRMin;
 }
-__host__ __device__ inline int class_rows_per_lane(int c) { return c < kRMax ? c + 1 : kRMax; }
+__host__ __device__ inline bool class_banded(int c) { return c >= kBandClass; }
+__host__ __device__ inline int class_rows_per_lane(int c) { return c < kBandClass ? c + 1 : c - kBandClass + kBandRMin; }
+// entry of the tuning arrays that applies to class c
+__host__ __device__ inline int tune_index(int c) { return c < kBandClass ? c : kBandClass; }
 
 // Model constants in the scaled-variable form used by the kernels, computed
 // on the device from the raw parameters (k_tables).
@@ -126,7 +140,7 @@ int pairs_blocks_per_cu(int cls, int fp64);
 constexpr int kCkMaxClass = 4;  // single-band classes 0..4 (1..5 rows per lane) have the form,
 constexpr int kCkBandRows = 4;  // and the banded class, in bands of 64 * 4 rows
 // rows per lane a class runs with in a given form
-inline int class_rows(int c, bool ck) { return ck && c == kRMax ? kCkBandRows : class_rows_per_lane(c); }
+inline int class_rows(int c, bool ck) { return ck && class_banded(c) ? kCkBandRows : class_rows_per_lane(c); }
 hipError_t launch_pairs_ck(int cls, int grid, const PairArgs& a, hipStream_t s);
 hipError_t launch_pair_one_ck(int cls, int64_t p, const PairArgs& a, hipStream_t s);
 int pairs_ck_blocks_per_cu(int cls);

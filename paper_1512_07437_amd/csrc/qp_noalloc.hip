@@ -197,7 +197,7 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
         ck[c] = !fp64 && recompute[c] != 0;
         const int R = qp::class_rows(c, ck[c]);
         const int H = qp::kWave * R;
-        const int nb = c == qp::kRMax ? (cls[c].mmax + H - 1) / H : 1;
+        const int nb = qp::class_banded(c) ? (cls[c].mmax + H - 1) / H : 1;
         const int cap = (int)std::max(1.0, std::min((double)cls[c].nmax, inv + 1.0));
         cargs[c] = qp::PairArgs{};
         qp::slot_layout(R, cls[c].mmax, cls[c].nmax, nb, cap, fp64, ck[c], &cargs[c]);

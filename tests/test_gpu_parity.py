@@ -128,6 +128,11 @@ EDGE = [
     ("lane_edges", [63, 64, 65, 128, 129]),
     ("band_edges", [511, 512, 513, 40]),
     ("two_bands", [1100, 90, 700]),
+    # one row sequence per banded class, bands of 64 R rows with
+    # R = ceil(m / (64 ceil(m / 512))): 513 -> 5 (320 + 193), 640 -> 5 (two
+    # full bands), 850 -> 7, 1000 -> 8 (512 + 488), 1025 -> 6 (384 + 384 +
+    # 257), 1152 -> 6 (three full bands), 1536 -> 8 (three full bands)
+    ("band_heights", [513, 640, 850, 1000, 1025, 1152, 1536, 90]),
 ]
 
 
@@ -145,8 +150,10 @@ def test_edge_shapes(B, params, name, lens):
             k += 1
 
 
-@pytest.mark.parametrize("name,lens", [e for e in EDGE if e[0] in ("lane_edges", "band_edges", "two_bands")],
-                         ids=["lane_edges", "band_edges", "two_bands"])
+_EDGE64 = ("lane_edges", "band_edges", "two_bands", "band_heights")
+
+
+@pytest.mark.parametrize("name,lens", [e for e in EDGE if e[0] in _EDGE64], ids=list(_EDGE64))
 def test_edge_shapes_fp64(B, params, name, lens):
     """The FP64 path on every single-band class boundary and on banded rows."""
     fam = W.make_family(len(lens), lens, 7, r_sub=0.3, r_indel=0.05)
