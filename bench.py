@@ -70,6 +70,61 @@ def class_kernels(B, plan, fp64: bool):
     return classes
 
 
+def consistency_extra(B, W, params, thresh: float, say, reps: int = 3, tree_threshold: int = 200,
+                      amplification: float = 3.0):
+    """Selective consistency on the device for the C2 family, after the timed
+    region: GPU posteriors, the guide tree on their distances, then the
+    relaxation of the device-resident all-pairs CSR through the third
+    sequences with max(d_xz, d_yz) <= tree_threshold (one pass for 50
+    sequences or more, two below), timed with HIP events on the run stream."""
+    import torch
+    fam = W.c2_family()
+    k = len(fam)
+    lens = [len(s) for s in fam]
+    d_seqs, d_off = B.device_inputs(fam, "cuda:0")
+    s = torch.cuda.current_stream()
+    plan = B.Plan(lens, params, thresh, nnz_capacity=-1)
+    try:
+        plan.run(d_seqs.data_ptr(), d_off.data_ptr(), s.cuda_stream)
+        dres = plan.sync()
+        host = plan.download()
+        joins, _ = B.guide_tree(host["dist"], k)
+        tdist = B.tree_distance(joins, k)
+        d_t = torch.from_numpy(tdist).to("cuda:0")
+        passes = 2 if k < 50 else 1
+        rx = B.Relax(lens, tree_threshold, amplification, passes, thresh, in_capacity=int(dres.nnz))
+        try:
+            rx.run(dres, int(dres.nnz), d_t.data_ptr(), s.cuda_stream)
+            rx.sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                rx.run(dres, int(dres.nnz), d_t.data_ptr(), s.cuda_stream)
+            e1.record(s)
+            out = rx.sync()
+            ms = e0.elapsed_time(e1) / reps
+            relax_bytes = rx.device_bytes()
+        finally:
+            rx.close()
+    finally:
+        plan.close()
+    # third sequences selected per pair: z with both tree-guided distances <= T
+    D = np.zeros((k, k), dtype=np.int64)
+    iu = np.triu_indices(k, 1)
+    D[iu] = tdist
+    D = D + D.T
+    M = (D <= tree_threshold) & ~np.eye(k, dtype=bool)
+    sel = (M.astype(np.int64) @ M.T.astype(np.int64))[iu]
+    n_pairs = k * (k - 1) // 2
+    r = {"workload": "C2: 200 seqs, L ~ U{250..350}, %d pairs" % n_pairs, "tree_threshold": tree_threshold,
+         "amplification": amplification, "passes": passes, "ms": round(ms, 3),
+         "pairs_per_s": round(n_pairs / (ms * 1e-3), 1), "entries_in": int(dres.nnz), "entries_out": int(out.nnz),
+         "third_sequences_per_pair_mean": round(float(sel.mean()), 2), "device_bytes": relax_bytes,
+         "where": "after the timed region, HIP events on the run stream"}
+    say("consistency on C2: %s" % r)
+    return r
+
+
 def committed_traffic(kernel: str, workload_key: str):
     """HBM bytes per launch (read, write) of `kernel` on `workload_key` from the
     committed counter summary, or None when the summary is missing or was
@@ -264,6 +319,8 @@ def main():
     ap.add_argument("--classes", default="table", choices=["table", "serial", "concurrent"],
                     help="kernel classes one after another on the run stream (serial) or side by side on "
                          "forked streams (concurrent); default: the tuning table's choice")
+    ap.add_argument("--no-consistency", action="store_true",
+                    help="skip the selective-consistency timing on the C2 family after the timed region")
     ap.add_argument("--no-alone", action="store_true",
                     help="skip the pass that times the dominant kernel with the device to itself")
     ap.add_argument("--recompute", default="table", choices=["table", "none", "all"],
@@ -476,13 +533,15 @@ def main():
                                      "classes_one_after_another_ms": round(a_kernel_ms, 4)}
         say("dominant kernel alone: %s" % (out.get("roofline_alone"),))
     del res
+    if args.workload == "c3" and not args.no_consistency and prec == B.QP_FP32_SCALED:
+        out.setdefault("extra", {})["consistency"] = consistency_extra(B, W, params, args.thresh, say)
     if args.workload == "c3" and args.c4_families > 0 and prec == B.QP_FP32_SCALED:
         # the metric's latency term: the C4 stream through the serving loop
         c4 = serve_stream(args, say, args.c4_families)
-        out["extra"] = {"c4": {k: c4[k] for k in (
+        out.setdefault("extra", {})["c4"] = {k: c4[k] for k in (
             "value", "unit", "p50_latency_ms", "p99_latency_ms", "queue_ms_p50_p99", "service_ms_p50_p99",
             "service_split_ms_p50", "offered_gcups", "wall_s", "max_abs_err_vs_oracle",
-            "max_abs_ea_err_vs_oracle", "oracle_checked_pairs") if k in c4}}
+            "max_abs_ea_err_vs_oracle", "oracle_checked_pairs") if k in c4}
         out["extra"]["c4"]["config"] = c4["config"]
         out["p99_family_latency_ms"] = c4["p99_latency_ms"]
         if c4["config"]["failed_families"]:
