@@ -533,7 +533,7 @@ def main():
                                      "classes_one_after_another_ms": round(a_kernel_ms, 4)}
         say("dominant kernel alone: %s" % (out.get("roofline_alone"),))
     del res
-    if args.workload == "c3" and not args.no_consistency and prec == B.QP_FP32_SCALED:
+    if args.workload in ("c2", "c3") and not args.no_consistency and prec == B.QP_FP32_SCALED:
         out.setdefault("extra", {})["consistency"] = consistency_extra(B, W, params, args.thresh, say)
     if args.workload == "c3" and args.c4_families > 0 and prec == B.QP_FP32_SCALED:
         # the metric's latency term: the C4 stream through the serving loop

@@ -36,7 +36,8 @@ namespace {
 
 using qp::kWave;
 constexpr int kRelaxWaves = 4;       // wavefronts per block
-constexpr int kMaxRelaxSeqs = 2048;  // the selection of a pair is a 32-bit mask per lane
+constexpr int kMaxRelaxSeqs = 2048;  // a selected sequence is an int16 in the LDS list
+constexpr int64_t kRelaxLds = 64 * 1024;  // dynamic LDS of a k_relax block
 
 struct Csr {
     const int64_t* row_off;  // [P + 1] into row_ptr
@@ -114,7 +115,13 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_transpose(
 }
 
 // one pass of the relaxation; out_* receive per-pair row pointers and the
-// kept entries at the pair's bound offset (stage_off), out_nnz the count
+// kept entries at the pair's bound offset (stage_off), out_nnz the count.
+// A wavefront relaxes its pair a block of B rows at a time: the selected
+// third sequences are compacted once into an LDS list, the block's rows get
+// B accumulator rows of acc_stride floats in LDS, and the (row, z) items of
+// the block are dealt over the lanes, so every lane follows its own chain of
+// dependent loads (row i of S_xz, then the rows of S_zy it points to) and the
+// chains of the block overlap instead of running one row after another.
 __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
     int32_t k, int64_t P, const int32_t* __restrict__ lens, const int32_t* __restrict__ pair_i,
     const int32_t* __restrict__ pair_j, Csr in, const int64_t* __restrict__ tr_row_off,
@@ -122,16 +129,18 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
     const int32_t* __restrict__ tdist, int32_t T, float h, float thresh, int32_t cap,
     const int64_t* __restrict__ out_row_off, int32_t* __restrict__ out_row_ptr, const int64_t* __restrict__ stage_off,
     int32_t* __restrict__ stage_col, float* __restrict__ stage_val, int64_t* __restrict__ out_nnz,
-    int* __restrict__ flags) {
-    __shared__ float acc_s[kRelaxWaves][qp::kMaxSeqLen];
+    int* __restrict__ flags, int32_t B, int32_t acc_stride) {
+    // dynamic LDS: [kRelaxWaves][B][acc_stride] accumulators, then
+    // [kRelaxWaves][k] selected third sequences
+    extern __shared__ float lds[];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    float* acc = acc_s[w];
+    float* acc = lds + (int64_t)w * B * acc_stride;
+    int16_t* zl = reinterpret_cast<int16_t*>(lds + (int64_t)kRelaxWaves * B * acc_stride) + (int64_t)w * k;
     for (int64_t p = (int64_t)blockIdx.x * kRelaxWaves + w; p < P; p += (int64_t)gridDim.x * kRelaxWaves) {
         const int x = __builtin_amdgcn_readfirstlane(pair_i[p]);
         const int y = __builtin_amdgcn_readfirstlane(pair_j[p]);
         const int m = lens[x], n = lens[y];
-        // selection: bit c of a lane's mask is z = 64 c + lane
-        uint32_t sel = 0;
+        // selection, compacted in increasing z
         int nsel = 0;
         for (int c = 0; c * kWave < k; ++c) {
             const int z = c * kWave + lane;
@@ -141,8 +150,12 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
                 const int dyz = tdist[pidx(min(y, z), max(y, z), k)];
                 s = max(dxz, dyz) <= T;
             }
-            sel |= s ? (1u << c) : 0u;
-            nsel += __popcll(__ballot(s));
+            const unsigned long long sm = __ballot(s);
+            if (s) {
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(sm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sm, 0));
+                zl[nsel + rank] = (int16_t)z;
+            }
+            nsel += __popcll(sm);
         }
         const float hxy = k <= 2 ? 1.f : 1.f + (h - 1.f) * (float)nsel / (float)(k - 2);
         const float own = 2.f * hxy;
@@ -152,15 +165,28 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
         int32_t* orp = out_row_ptr + out_row_off[p];
         const int64_t obase = stage_off[p];
         int count = 0;
-        for (int i = 0; i < m; ++i) {
-            for (int c = lane; c < n; c += kWave) acc[c] = 0.f;
-            for (int e = rxy[i] + lane; e < rxy[i + 1]; e += kWave) {
+        for (int i0 = 0; i0 < m; i0 += B) {
+            const int nb = min(B, m - i0);
+            for (int c = lane; c < nb * acc_stride; c += kWave) acc[c] = 0.f;
+            // the pair's own entries, amplified (rows i0 .. i0+nb-1 are one
+            // contiguous run of its CSR)
+            const int e_lo = rxy[i0], e_hi = rxy[i0 + nb];
+            for (int e = e_lo + lane; e < e_hi; e += kWave) {
+                int r = 0;
+                while (r + 1 < nb && rxy[i0 + r + 1] <= e) ++r;
                 const int j = in.col[bxy + e];
-                if (j >= 0 && j < n) acc[j] = own * in.val[bxy + e];
+                if (j >= 0 && j < n) acc[r * acc_stride + j] = own * in.val[bxy + e];
             }
-            for (int c = 0; c * kWave < k; ++c) {
-                if (!((sel >> c) & 1u)) continue;
-                const int z = c * kWave + lane;
+            // (row, z) items of the block over the lanes, z-major: lanes next
+            // to each other take the block's consecutive rows of one S_xz, whose
+            // row pointers and entries share cache lines, and whose entries point
+            // to neighbouring rows of S_zy
+            const int items = nb * nsel;
+            for (int q = lane; q < items; q += kWave) {
+                const int zi = q / nb;
+                const int r = q - zi * nb;
+                const int z = zl[zi];
+                const int i = i0 + r;
                 // row i of S_xz: pair (x, z) as stored, or (z, x) transposed
                 const bool xa = x < z;
                 const int64_t pxz = xa ? pidx(x, z, k) : pidx(z, x, k);
@@ -175,35 +201,41 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
                 const int32_t* cb = za ? in.col : tr_col;
                 const float* vb = za ? in.val : tr_val;
                 const int64_t bb = in.nnz_off[pzy];
-                for (int ea = ra[i]; ea < ra[i + 1]; ++ea) {
+                float* accr = acc + r * acc_stride;
+                const int ea1 = ra[i + 1];
+                for (int ea = ra[i]; ea < ea1; ++ea) {
                     const int kk = ca[ba + ea];
                     const float v1 = va[ba + ea];
-                    for (int eb = rb[kk]; eb < rb[kk + 1]; ++eb) {
+                    const int eb1 = rb[kk + 1];
+                    for (int eb = rb[kk]; eb < eb1; ++eb) {
                         const int j = cb[bb + eb];
-                        if (j >= 0 && j < n) atomicAdd(&acc[j], v1 * vb[bb + eb]);
+                        if (j >= 0 && j < n) atomicAdd(&accr[j], v1 * vb[bb + eb]);
                     }
                 }
             }
-            // scale, threshold, compact in column order (at most cap per row)
-            int rc = 0;
-            for (int c0 = 0; c0 < n; c0 += kWave) {
-                const int c = c0 + lane;
-                const float v = c < n ? acc[c] * invW : 0.f;
-                const bool hit = c < n && v >= thresh;
-                const unsigned long long hm = __ballot(hit);
-                const int rank = rc + __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (kWave - lane))));
-                if (hit && rank < cap) {
-                    stage_col[obase + count + rank] = c;
-                    stage_val[obase + count + rank] = v;
+            // scale, threshold, compact each row in column order (at most cap)
+            for (int r = 0; r < nb; ++r) {
+                const float* accr = acc + r * acc_stride;
+                int rc = 0;
+                for (int c0 = 0; c0 < n; c0 += kWave) {
+                    const int c = c0 + lane;
+                    const float v = c < n ? accr[c] * invW : 0.f;
+                    const bool hit = c < n && v >= thresh;
+                    const unsigned long long hm = __ballot(hit);
+                    const int rank = rc + __popcll(hm & (lane == 0 ? 0ull : (~0ull >> (kWave - lane))));
+                    if (hit && rank < cap) {
+                        stage_col[obase + count + rank] = c;
+                        stage_val[obase + count + rank] = v;
+                    }
+                    rc += __popcll(hm);
                 }
-                rc += __popcll(hm);
+                if (rc > cap) {
+                    if (lane == 0) atomicOr(flags, 2);
+                    rc = cap;
+                }
+                count += rc;
+                if (lane == 0) orp[i0 + r + 1] = count;
             }
-            if (rc > cap) {
-                if (lane == 0) atomicOr(flags, 2);
-                rc = cap;
-            }
-            count += rc;
-            if (lane == 0) orp[i + 1] = count;
         }
         if (lane == 0) {
             orp[0] = 0;
@@ -228,6 +260,9 @@ struct qp_relax {
     float thresh = 0.f;
     int32_t cap = 1;
     int n_cu = 1;
+    int32_t rows_per_block = 1;  // rows a wavefront relaxes at once (B)
+    int32_t acc_stride = 1;      // LDS accumulator row (>= the longest second sequence)
+    int64_t lds_bytes = 0;       // dynamic LDS of a k_relax block
     std::vector<int32_t> lens;
     int64_t total_rows = 0, tr_rows = 0, bound = 0, in_cap = 0;
     std::vector<void*> allocs;
@@ -311,6 +346,21 @@ qp_status qp_relax_create(const int32_t* lens, int32_t n, int64_t in_capacity, i
     r->thresh = thresh;
     r->cap = (int32_t)std::min<double>(qp::kMaxSeqLen, std::floor(1.0 / (double)thresh) + 1.0);
     r->lens.assign(lens, lens + n);
+    {
+        // B accumulator rows per wavefront, as many (up to 8) as fit beside
+        // the selection lists in the LDS a block may hold: the more rows of
+        // one S_xz neighbouring lanes take, the more their loads share lines
+        const int32_t nmax = *std::max_element(lens, lens + n);
+        r->acc_stride = nmax + (nmax & 1);
+        const int64_t zl_bytes = (int64_t)kRelaxWaves * n * 2;
+        const int64_t per_row = (int64_t)kRelaxWaves * r->acc_stride * 4;
+        r->rows_per_block = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, (kRelaxLds - zl_bytes) / per_row));
+        r->lds_bytes = (int64_t)r->rows_per_block * per_row + zl_bytes;
+        if (r->lds_bytes > kRelaxLds) {
+            delete r;
+            return qp::fail_msg(QP_EINVAL, "the relaxation's LDS (%lld bytes) does not fit a block", (long long)r->lds_bytes);
+        }
+    }
     const int64_t P = r->P;
     std::vector<int32_t> pi((size_t)std::max<int64_t>(P, 1)), pj((size_t)std::max<int64_t>(P, 1));
     std::vector<int64_t> row_off((size_t)P + 1), tr_off((size_t)P + 1), stage_off((size_t)P + 1);
@@ -418,10 +468,11 @@ qp_status qp_relax_run(qp_relax* r, const qp_device_result* in, int64_t in_nnz, 
         hipLaunchKernelGGL(k_transpose, dim3(grid), dim3(kWave * kRelaxWaves), 0, s, r->k, r->P, r->d_lens, r->d_pi,
                            r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col, r->d_tr_val, r->d_flags);
         RX_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_relax, dim3(grid), dim3(kWave * kRelaxWaves), 0, s, r->k, r->P, r->d_lens, r->d_pi,
-                           r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col, r->d_tr_val, d_tdist, r->T,
-                           (float)r->h, r->thresh, r->cap, r->d_row_off, r->d_out_row_ptr[q], r->d_stage_off,
-                           r->d_stage_col, r->d_stage_val, r->d_out_nnz[q], r->d_flags);
+        hipLaunchKernelGGL(k_relax, dim3(grid), dim3(kWave * kRelaxWaves), (size_t)r->lds_bytes, s, r->k, r->P,
+                           r->d_lens, r->d_pi, r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col,
+                           r->d_tr_val, d_tdist, r->T, (float)r->h, r->thresh, r->cap, r->d_row_off,
+                           r->d_out_row_ptr[q], r->d_stage_off, r->d_stage_col, r->d_stage_val, r->d_out_nnz[q],
+                           r->d_flags, r->rows_per_block, r->acc_stride);
         RX_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(r->d_out_nnz[q] + r->P), 2);
         RX_TRY(hipGetLastError());
