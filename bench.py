@@ -316,6 +316,9 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the run, copy this many MiB device-to-device (a known-size kernel that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--orient", default="table", choices=["table", "off", "on"],
+                    help="sweep each pair in the orientation the cost model picks (on) or with the first "
+                         "sequence as rows (off); default: the tuning table's choice")
     ap.add_argument("--classes", default="table", choices=["table", "serial", "concurrent"],
                     help="kernel classes one after another on the run stream (serial) or side by side on "
                          "forked streams (concurrent); default: the tuning table's choice")
@@ -345,6 +348,8 @@ def main():
         B.set_tuning(recompute=[1, 1, 1, 1, 1, 0, 0, 0, 1] if args.recompute == "all" else [0] * 9)
     if args.classes != "table":
         B.set_tuning(concurrent_classes=int(args.classes == "concurrent"))
+    if args.orient != "table":
+        B.set_tuning(orient=int(args.orient == "on"))
     say("pair-kernel forms (1 = checkpointed) per class: %s; classes %s" % (
         B.get_tuning()["recompute"], "concurrent" if B.get_tuning()["concurrent_classes"] else "one after another"))
     if args.workload == "c4":
@@ -441,7 +446,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "pairs": n_pairs, "cells": cells, "thresh": args.thresh,
                    "graph": not args.no_graph, "nnz": int(res["nnz"]),
-                   "classes": "concurrent" if B.get_tuning()["concurrent_classes"] else "serial"},
+                   "classes": "concurrent" if B.get_tuning()["concurrent_classes"] else "serial",
+                   "orient": bool(B.get_tuning()["orient"])},
         "pairs_per_s": round(n_pairs / (dt / args.steps), 1),
         "kernel_ms": round(kernel_ms, 4),
         "pipeline_ms": round(pipe_ms, 4),

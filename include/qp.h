@@ -312,6 +312,12 @@ qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
  * streams (one class's tail overlaps the next one's work); 0 runs them one
  * after another on the run stream, largest rows per lane first, each with
  * the whole device (and one workspace shared by all classes).  Default 1.
+ * orient = 1 lets a plan sweep a pair with its second sequence as rows when
+ * a cost model of the kernel classes (lane-steps of the sweep times a
+ * measured cost per class) finds that cheaper and both models' tables are
+ * exactly symmetric, so that P(y, x) = P(x, y)^T; the output rows are the
+ * first sequence's either way.  0 sweeps every pair with the first
+ * sequence as rows.  Default 1; qp_posteriors_noalloc never transposes.
  * Filled in by the project's autotuner (paper_1512_07437_amd/autotune.py)
  * from measurements per length bucket.
  */
@@ -320,6 +326,7 @@ typedef struct {
     double waves_frac[9];
     int32_t recompute[9];
     int32_t concurrent_classes;
+    int32_t orient;
 } qp_tuning;
 
 /* Set the table (NULL restores the default); QP_EINVAL for a value out of

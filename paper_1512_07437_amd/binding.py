@@ -75,7 +75,7 @@ _P = ctypes.POINTER
 _u8pp = _P(_P(ctypes.c_uint8))
 class qp_tuning(ctypes.Structure):
     _fields_ = [("rows_per_lane", ctypes.c_int32 * 8), ("waves_frac", ctypes.c_double * 9),
-                ("recompute", ctypes.c_int32 * 9), ("concurrent_classes", ctypes.c_int32)]
+                ("recompute", ctypes.c_int32 * 9), ("concurrent_classes", ctypes.c_int32), ("orient", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -159,11 +159,13 @@ TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_g
 
 
 def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Optional[Sequence[float]] = None,
-               recompute: Optional[Sequence[int]] = None, concurrent_classes: Optional[int] = None):
+               recompute: Optional[Sequence[int]] = None, concurrent_classes: Optional[int] = None,
+               orient: Optional[int] = None):
     """Process-wide tuning table for plans made afterwards (qp_set_tuning);
-    entries left None keep their current values; None for all four
+    entries left None keep their current values; None for all of them
     restores the default."""
-    if rows_per_lane is None and waves_frac is None and recompute is None and concurrent_classes is None:
+    if (rows_per_lane is None and waves_frac is None and recompute is None and concurrent_classes is None
+            and orient is None):
         _check(lib.qp_set_tuning(None))
         return
     t = get_tuning()
@@ -175,6 +177,7 @@ def set_tuning(rows_per_lane: Optional[Sequence[int]] = None, waves_frac: Option
     v.waves_frac[:] = [float(x) for x in w]
     v.recompute[:] = [int(x) for x in c]
     v.concurrent_classes = int(t["concurrent_classes"] if concurrent_classes is None else concurrent_classes)
+    v.orient = int(t["orient"] if orient is None else orient)
     _check(lib.qp_set_tuning(ctypes.byref(v)))
 
 
@@ -182,7 +185,8 @@ def get_tuning() -> Dict[str, list]:
     t = qp_tuning()
     _check(lib.qp_get_tuning(ctypes.byref(t)))
     return {"rows_per_lane": list(t.rows_per_lane), "waves_frac": list(t.waves_frac),
-            "recompute": list(t.recompute), "concurrent_classes": int(t.concurrent_classes)}
+            "recompute": list(t.recompute), "concurrent_classes": int(t.concurrent_classes),
+            "orient": int(t.orient)}
 
 
 def load_tuning(path: str = TUNING_PATH) -> bool:
@@ -192,7 +196,7 @@ def load_tuning(path: str = TUNING_PATH) -> bool:
         return False
     with open(path) as f:
         d = json.load(f)
-    set_tuning(d["rows_per_lane"], d["waves_frac"], d.get("recompute"), d.get("concurrent_classes"))
+    set_tuning(d["rows_per_lane"], d["waves_frac"], d.get("recompute"), d.get("concurrent_classes"), d.get("orient"))
     return True
 
 

@@ -32,6 +32,7 @@ void default_tuning(qp_tuning* t) {
         t->recompute[c] = c >= 2 && c <= 4 ? 1 : 0;
     }
     t->concurrent_classes = 1;
+    t->orient = 1;
 }
 qp_tuning g_tuning = [] {
     qp_tuning t;
@@ -137,6 +138,9 @@ struct qp_plan {
     // pair_cls holds each pair's kernel class
     bool per_pair = false;
     std::vector<uint8_t> pair_cls;
+    // per pair: 1 = swept with the second sequence as rows (empty: none is)
+    std::vector<uint8_t> tr;
+    uint8_t* d_tr = nullptr;
     // tuning in force when the plan was made
     qp::ClassMap cmap{};
     double waves_frac[qp::kClasses] = {};
@@ -363,6 +367,42 @@ static void set_class_args(qp_plan* pl) {
 
 // allocation of all plan buffers (needs pool_cap and grids); with `dry`
 // only adds up the bytes it would allocate
+// ns per lane-row-step of each kernel class (C3, each class alone, default
+// forms): the cost model that picks a pair's orientation
+constexpr double kSlotCost[qp::kClasses] = {4.61, 3.42, 2.89, 2.64, 2.50, 3.27, 3.26, 3.23, 3.42, 3.32, 2.98, 2.82};
+
+// modelled time of sweeping m rows by c columns: per band, c + L - 1 steps
+// of 64 lanes x R rows (L lanes in use), times the class's cost per step
+static double sweep_cost(int32_t m, int32_t c, const qp::ClassMap& map) {
+    const int cls = qp::pair_class(m, map);
+    const int R = qp::class_rows_per_lane(cls);
+    const int H = qp::kWave * R;
+    const int nb = qp::class_banded(cls) ? (m + H - 1) / H : 1;
+    double slots = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const int rows = std::min(H, m - b * H);
+        const int L = (rows + R - 1) / R;
+        slots += (double)(c + L - 1) * qp::kWave * R;
+    }
+    return slots * kSlotCost[cls];
+}
+
+// the tables of both models are exactly symmetric (then P(y, x) = P(x, y)^T
+// to the last bit of the inputs)
+static bool symmetric_tables(const qp_params& p) {
+    for (int a = 0; a < QP_ALPHA; ++a)
+        for (int b = a + 1; b < QP_ALPHA; ++b)
+            if (p.joint[a * QP_ALPHA + b] != p.joint[b * QP_ALPHA + a] ||
+                p.score[a * QP_ALPHA + b] != p.score[b * QP_ALPHA + a])
+                return false;
+    return true;
+}
+
+// rows of pair p's sweep (its first sequence's m unless it is transposed)
+static int32_t swept_rows(const qp_plan* pl, int64_t p, int32_t m, int32_t c) {
+    return !pl->tr.empty() && pl->tr[(size_t)p] ? c : m;
+}
+
 // Streams of a plan's classes: with classes side by side, the present
 // classes from the largest down are dealt round-robin over min(present,
 // kMaxSide) side streams; one after another, they all share the run stream.
@@ -419,6 +459,7 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
         ALLOC(pl->d_list_i, P);
         ALLOC(pl->d_list_j, P);
     }
+    if (!pl->tr.empty()) ALLOC(pl->d_tr, P);
     ALLOC(pl->d_pi, P);
     ALLOC(pl->d_pj, P);
     ALLOC(pl->d_rowoff, P + 1);
@@ -460,6 +501,7 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
         HIP_TRY(hipMemcpy(pl->d_list_i, pl->list_i.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(pl->d_list_j, pl->list_j.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
     }
+    if (!pl->tr.empty()) HIP_TRY(hipMemcpy(pl->d_tr, pl->tr.data(), (size_t)P, hipMemcpyHostToDevice));
     qp::DevParams dp{};
     std::memcpy(dp.joint, pl->params.joint, sizeof(dp.joint));
     std::memcpy(dp.score, pl->params.score, sizeof(dp.score));
@@ -481,6 +523,7 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     a.seq_off = pl->d_seqa_off;
     a.pair_i = pl->d_pi;
     a.pair_j = pl->d_pj;
+    a.tr = pl->d_tr;
     a.queue = pl->d_queue;
     a.n_pairs = P;
     a.queue_head = pl->d_ints + kIntHeads;
@@ -490,6 +533,7 @@ static qp_status plan_alloc_all(qp_plan* pl, int64_t* dry = nullptr) {
     a.col0 = pl->d_col0;
     a.consts = pl->d_consts;
     a.thresh = pl->thresh;
+    a.cap_thresh = (int)std::min<double>(qp::kMaxSeqLen + 1, std::floor(1.0 / (double)pl->thresh) + 1.0);
     a.row_off = pl->d_rowoff;
     a.row_ptr = pl->d_rowptr;
     a.pair_nnz = pl->d_nnz;
@@ -520,7 +564,7 @@ static qp_status enqueue_pipeline(qp_plan* pl, hipStream_t s, int ev_set, bool c
     HIP_TRY(qp::launch_stage_seqs(pl->n, alphabet_of(&pl->params), pl->in_seqs, pl->in_off, pl->d_lens, pl->d_seqa_off, pl->d_seqa,
                                   pl->d_ints + kIntFlags, s));
     HIP_TRY(qp::launch_tables(pl->d_params, pl->d_tab, pl->d_consts, pl->d_col0, pl->mmax, pl->fp64, s));
-    HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
+    HIP_TRY(qp::launch_setup(pl->n, pl->d_lens, pl->d_list_i, pl->d_list_j, pl->d_tr, P, pl->d_pi, pl->d_pj, pl->d_rowoff,
                              pl->d_key, pl->d_ints + kIntHist, pl->d_nnz, pl->cmap, s));
     HIP_TRY(qp::launch_bins(pl->d_ints + kIntHist, pl->d_bin_start, s));
     HIP_TRY(qp::launch_fill_queue(P, pl->d_key, pl->d_bin_start, pl->d_ints + kIntFill, pl->d_queue, s));
@@ -739,6 +783,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     pl->P = P;
     pl->all_pairs = all;
     pl->lens.assign(lens, lens + n);
+    bool orient = false;
     {
         std::lock_guard<std::mutex> g(g_tuning_mu);
         for (int r = 0; r < qp::kRMax; ++r) pl->cmap.c[r] = (int8_t)(g_tuning.rows_per_lane[r] - 1);
@@ -747,6 +792,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
             pl->recompute[c] = g_tuning.recompute[qp::tune_index(c)];
         }
         pl->single_stream = g_tuning.concurrent_classes == 0;
+        orient = g_tuning.orient != 0;
     }
     if (!all) {
         pl->list_i.assign(pair_i, pair_i + P);
@@ -763,14 +809,29 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     const double inv = std::floor(1.0 / (double)thresh);
     const int per_row = (int)std::max(1.0, std::min(16.0, inv));
     const int per_row_lo = (int)std::max(1.0, std::min(8.0, inv));
+    // orientation: with symmetric model tables the posterior matrix of (y, x)
+    // is the transpose of (x, y)'s, so a pair may be swept with either
+    // sequence as rows; each pair takes the orientation of the lower
+    // modelled cost, its output rows staying the first sequence's
+    const bool may_transpose = orient && symmetric_tables(*params);
+    std::vector<uint8_t> tr((size_t)(may_transpose ? P : 0), 0);
+    bool any_tr = false;
+    int64_t q = 0;
     auto count = [&](int32_t m, int32_t c) {
-        qp_plan::ClassPlan& cp = pl->cls[qp::pair_class(m, pl->cmap)];
+        const bool t = may_transpose && sweep_cost(c, m, pl->cmap) < sweep_cost(m, c, pl->cmap);
+        if (t) {
+            tr[(size_t)q] = 1;
+            any_tr = true;
+        }
+        ++q;
+        const int32_t ms = t ? c : m, cs = t ? m : c;  // rows and columns of the sweep
+        qp_plan::ClassPlan& cp = pl->cls[qp::pair_class(ms, pl->cmap)];
         cp.pairs += 1;
         cp.cells += (int64_t)m * c;
-        cp.mmax = std::max(cp.mmax, m);
-        cp.nmax = std::max(cp.nmax, c);
-        pl->mmax = std::max(pl->mmax, m);
-        pl->nmax = std::max(pl->nmax, c);
+        cp.mmax = std::max(cp.mmax, ms);
+        cp.nmax = std::max(cp.nmax, cs);
+        pl->mmax = std::max(pl->mmax, ms);
+        pl->nmax = std::max(pl->nmax, cs);
         rows += m + 1;
         est += (int64_t)m * std::min(per_row, c);
         est_lo += (int64_t)m * std::min(per_row_lo, c);
@@ -782,6 +843,7 @@ qp_status qp::plan_shape(const int32_t* lens, int32_t n, const int32_t* pair_i, 
     } else {
         for (int64_t k = 0; k < P; ++k) count(lens[pair_i[k]], lens[pair_j[k]]);
     }
+    if (any_tr) pl->tr.swap(tr);
     pl->total_rows = rows;
 
     // persistent grid per class: enough waves to fill every SIMD at the
@@ -1126,6 +1188,7 @@ qp_status qp_set_tuning(const qp_tuning* t) {
                 return fail(QP_EINVAL, "waves_frac[%d] = %g is not in (0, 1]", c, t->waves_frac[c]);
         if (t->concurrent_classes != 0 && t->concurrent_classes != 1)
             return fail(QP_EINVAL, "concurrent_classes = %d is not 0 or 1", t->concurrent_classes);
+        if (t->orient != 0 && t->orient != 1) return fail(QP_EINVAL, "orient = %d is not 0 or 1", t->orient);
         v = *t;
     }
     std::lock_guard<std::mutex> g(g_tuning_mu);
@@ -1151,9 +1214,12 @@ qp_status qp_plan_set_per_pair(qp_plan* pl, int32_t on) {
         int64_t p = 0;
         if (pl->all_pairs) {
             for (int32_t i = 0; i + 1 < pl->n; ++i)
-                for (int32_t j = i + 1; j < pl->n; ++j) pl->pair_cls[p++] = (uint8_t)qp::pair_class(pl->lens[i], pl->cmap);
+                for (int32_t j = i + 1; j < pl->n; ++j, ++p)
+                    pl->pair_cls[p] = (uint8_t)qp::pair_class(swept_rows(pl, p, pl->lens[i], pl->lens[j]), pl->cmap);
         } else {
-            for (; p < pl->P; ++p) pl->pair_cls[p] = (uint8_t)qp::pair_class(pl->lens[pl->list_i[p]], pl->cmap);
+            for (; p < pl->P; ++p)
+                pl->pair_cls[p] = (uint8_t)qp::pair_class(
+                    swept_rows(pl, p, pl->lens[pl->list_i[p]], pl->lens[pl->list_j[p]]), pl->cmap);
         }
     }
     pl->per_pair = on != 0;

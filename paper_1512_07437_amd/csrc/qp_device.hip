@@ -370,6 +370,45 @@ __device__ void fwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
     }
 }
 
+// Hit log of one backward step: the rows of hbits hit at column j.  Each
+// record is (output row, rank from the output row's end, output column,
+// value); the wave appends its records as one contiguous run per row index.
+// Normal pair: output row = the row, rank = its hits so far (cnt, already
+// counting this one), columns met in decreasing order.  Transposed pair
+// (swept with the second sequence as rows): output row = the column j-1,
+// output column = the row; a column meets its rows in decreasing order, the
+// lane's rows at this step last (highest row first), so a row's rank is the
+// column's hits before this step (one LDS atomic per lane adds them all)
+// plus the lane's hit rows above it.  Hits past a row's capacity are counted
+// but not logged.  The log holds log_cap records; a pair whose hits would
+// pass that (not possible for posteriors: at most min(m, n) / thresh of them
+// reach the threshold) stops logging and is reported (flag bit 1).
+template <int R>
+__device__ __forceinline__ void log_hits(int hbits, bool trp, int* __restrict__ colcnt, const int (&cnt)[R],
+                                         int cap, int j, int r0, int lane, const float (&pv)[R],
+                                         int4* __restrict__ hitlog, int& nlog, int log_cap, int* __restrict__ flags) {
+    if (!__ballot(hbits != 0)) return;
+    int old = 0;
+    if (trp && hbits != 0) old = atomicAdd(&colcnt[j - 1], __popc((unsigned)hbits));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool h = ((hbits >> r) & 1) != 0;
+        const int rk = trp ? old + __popc((unsigned)hbits >> (r + 1)) : cnt[r] - 1;
+        const bool keep = h && rk < cap;
+        const unsigned long long km = __ballot(keep);
+        if (km) {
+            const int rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0));
+            const int row = r0 + lane * R + r;
+            if (keep && nlog + rank < log_cap)
+                hitlog[nlog + rank] = make_int4(trp ? j - 1 : row, rk, trp ? row : j - 1, __float_as_int(pv[r]));
+            const int nn = nlog + __popcll(km);
+            if (nn > log_cap && lane == 0) atomicOr(flags, 2);
+            nlog = __builtin_amdgcn_readfirstlane(min(nn, log_cap));
+        }
+    }
+}
+
 // --------------------------------------------------------------- backward
 // FIRST / LAST: the band is the top / bottom band of the pair (band position
 // modes as in the forward routine).
@@ -380,7 +419,8 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
                          const BwdBnd<T>* __restrict__ bin, BwdBnd<T>* __restrict__ bout, T invZH, T invZP, int ezH,
                          int ezP, float thresh, int cap, int4* __restrict__ hitlog, int& nlog,
                          int32_t* __restrict__ rowcnt, int* __restrict__ flags,
-                         double& a11, bool rt_first, bool rt_last) {
+                         double& a11, bool rt_first, bool rt_last, bool trp, int* __restrict__ colcnt,
+                         int log_cap) {
     using V2 = typename Pair2<T>::type;
     const bool FIRST = band_is(FM, rt_first), LAST = band_is(LM, rt_last);
     const bool used = lane < L;
@@ -554,17 +594,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
         // sparse 4-byte writes); record = (row, rank from the row's end,
         // column, value).  Uniform control flow keeps the log position in a
         // scalar; a row past its capacity keeps counting and is reported.
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const bool keep = ((hbits >> r) & 1) != 0 && cnt[r] <= cap;
-            const unsigned long long km = __ballot(keep);
-            if (km) {
-                const int rank =
-                    __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0));
-                if (keep) hitlog[nlog + rank] = make_int4(r0 + lane * R + r, cnt[r] - 1, j - 1, __float_as_int(pv[r]));
-                nlog = __builtin_amdgcn_readfirstlane(nlog + __popcll(km));
-            }
-        }
+        log_hits<R>(hbits, trp, colcnt, cnt, cap, j, r0, lane, pv, hitlog, nlog, log_cap, flags);
         bT = rT;
         bgT = rgT;
         bA = rA;
@@ -600,7 +630,7 @@ __device__ void bwd_band(int lane, const uint8_t* __restrict__ x, const uint8_t*
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = lane * R + r;
-        if (used && row < rows) {
+        if (!trp && used && row < rows) {
             int c = cnt[r];
             if (c > cap) {
                 atomicOr(flags, 2);
@@ -662,12 +692,38 @@ __device__ void finish_pair(const PairArgs& a, int lane, int64_t p, int m, int n
 }
 
 // ------------------------------------------------------------ one pair
+// Output row counts of a transposed pair: the LDS column counts, cut to
+// the row capacity (and reported past it), become the row counts the
+// output's row pointers are scanned from.
+__device__ __forceinline__ void zero_col_counts(int lane, int n, int* __restrict__ colcnt) {
+    for (int jj = lane; jj < n; jj += kWave) colcnt[jj] = 0;
+}
+__device__ __forceinline__ void col_counts_to_rows(const PairArgs& a, int lane, int n, int cap,
+                                                   const int* __restrict__ colcnt, int32_t* __restrict__ rowcnt) {
+    for (int jj = lane; jj < n; jj += kWave) {
+        int c = colcnt[jj];
+        if (c > cap) {
+            atomicOr(a.flags, 2);
+            c = cap;
+        }
+        rowcnt[jj] = c;
+    }
+}
+// entries an output row of the pair may hold: the class's staging capacity,
+// or for a transposed pair min(its rows, floor(1 / thresh) + 1)
+__device__ __forceinline__ int out_row_cap(const PairArgs& a, bool trp, int m) {
+    return trp ? min(m, a.cap_thresh) : a.cap;
+}
+
 // Forward sweep over the bands top to bottom, backward sweep bottom to top,
-// then the pair's output.  RB rows per lane, bands of kWave * RB rows.
+// then the pair's output.  RB rows per lane, bands of kWave * RB rows.  A
+// transposed pair (trp) is swept with the second sequence as x: the output
+// rows are then the sweep's columns, counted in colcnt.
 template <int RB, typename T, bool MULTI>
 __device__ __forceinline__ void pair_bands(const PairArgs& a, int lane, char* slot,
                                            const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p, int m,
-                                           int n, const uint8_t* x, const uint8_t* y) {
+                                           int n, const uint8_t* x, const uint8_t* y, bool trp,
+                                           int* __restrict__ colcnt) {
     using V2 = typename Pair2<T>::type;
     const int H = kWave * RB;
     const int nb = MULTI ? (m + H - 1) / H : 1;
@@ -676,6 +732,7 @@ __device__ __forceinline__ void pair_bands(const PairArgs& a, int lane, char* sl
     FwdBnd<T>* fb = reinterpret_cast<FwdBnd<T>*>(slot + a.off_fb);
     BwdBnd<T>* bb = reinterpret_cast<BwdBnd<T>*>(slot + a.off_bb);
     int4* hitlog = reinterpret_cast<int4*>(slot + a.off_log);
+    const int log_cap = (int)((a.slot_bytes - a.off_log) / (int64_t)sizeof(int4));
     int nlog = 0;
 
     T zH = T(1), zP = T(1);
@@ -707,6 +764,8 @@ __device__ __forceinline__ void pair_bands(const PairArgs& a, int lane, char* sl
     const T invZP = T(1.0 - a.consts->w_hmm) / zP;
     int32_t* rp = a.row_ptr + a.row_off[p];
     double a11 = 0.0;
+    const int ocap = out_row_cap(a, trp, m);
+    if (trp) zero_col_counts(lane, n, colcnt);
     for (int b = nb - 1; b >= 0; --b) {
         const int r0 = b * H;
         const int rows = min(H, m - r0);
@@ -719,28 +778,44 @@ __device__ __forceinline__ void pair_bands(const PairArgs& a, int lane, char* sl
         // lane L-1 below it reads a boundary record or nothing)
         if (!MULTI)
             bwd_band<RB, T, 1, 1>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH, ezP,
-                                  a.thresh, a.cap, hitlog, nlog, rp + 1, a.flags, a11, true, true);
+                                  a.thresh, ocap, hitlog, nlog, rp + 1, a.flags, a11, true, true, trp, colcnt,
+                                  log_cap);
         else if (b == nb - 1)
             bwd_band<RB, T, kBandRuntime, 1>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH,
-                                             ezP, a.thresh, a.cap, hitlog, nlog, rp + 1, a.flags, a11, b == 0, true);
+                                             ezP, a.thresh, ocap, hitlog, nlog, rp + 1, a.flags, a11, b == 0, true,
+                                             trp, colcnt, log_cap);
         else
             bwd_band<RB, T, kBandRuntime, 0>(lane, x, y, n, r0, rows, L, tab, k, sp, ex, bi, bo, invZH, invZP, ezH,
-                                             ezP, a.thresh, a.cap, hitlog, nlog, rp + 1, a.flags, a11, b == 0, false);
+                                             ezP, a.thresh, ocap, hitlog, nlog, rp + 1, a.flags, a11, b == 0, false,
+                                             trp, colcnt, log_cap);
         __threadfence_block();
     }
-    finish_pair(a, lane, p, m, n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
+    if (trp) col_counts_to_rows(a, lane, n, ocap, colcnt, rp + 1);
+    finish_pair(a, lane, p, trp ? n : m, trp ? m : n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
+}
+
+// the pair's two sequences in the order it is swept: x (rows), y (columns)
+struct PairSeqs {
+    int xi, yi;
+    bool trp;
+};
+__device__ __forceinline__ PairSeqs pair_seqs(const PairArgs& a, int64_t p) {
+    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
+    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
+    const bool trp = a.tr && __builtin_amdgcn_readfirstlane((int)a.tr[p]) != 0;
+    return PairSeqs{trp ? pj : pi, trp ? pi : pj, trp};
 }
 
 template <int R, typename T, bool MULTI>
 __device__ __forceinline__ void process_pair(const PairArgs& a, int lane, char* slot,
-                                             const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p) {
-    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
-    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
-    const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
-    const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
-    const uint8_t* x = a.seqs + uniform64(a.seq_off[pi]);
-    const uint8_t* y = a.seqs + uniform64(a.seq_off[pj]);
-    pair_bands<R, T, MULTI>(a, lane, slot, tab, k, p, m, n, x, y);
+                                             const typename Pair2<T>::type* tab, const Coef<T>& k, int64_t p,
+                                             int* __restrict__ colcnt) {
+    const PairSeqs ps = pair_seqs(a, p);
+    const int m = __builtin_amdgcn_readfirstlane(a.lens[ps.xi]);
+    const int n = __builtin_amdgcn_readfirstlane(a.lens[ps.yi]);
+    const uint8_t* x = a.seqs + uniform64(a.seq_off[ps.xi]);
+    const uint8_t* y = a.seqs + uniform64(a.seq_off[ps.yi]);
+    pair_bands<R, T, MULTI>(a, lane, slot, tab, k, p, m, n, x, y, ps.trp, colcnt);
 }
 
 // One persistent launch per kernel class: waves pop pairs of their class
@@ -749,6 +824,7 @@ template <int R, typename T, bool MULTI>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
     using V2 = typename Pair2<T>::type;
     __shared__ V2 tab[kTabRows * kTabW];
+    __shared__ int colcnt_s[kWavesPerBlock * kMaxSeqLen];  // output row counts of a transposed pair
     const V2* gtab = reinterpret_cast<const V2*>(a.tab);
     for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
     __syncthreads();
@@ -773,7 +849,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
         q = __builtin_amdgcn_readfirstlane(q) + seg_begin;
         if (q >= seg_end) break;
         const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
-        process_pair<R, T, MULTI>(a, lane, slot, tab, k, p);
+        process_pair<R, T, MULTI>(a, lane, slot, tab, k, p, colcnt_s + (threadIdx.x >> 6) * kMaxSeqLen);
     }
 }
 
@@ -784,6 +860,7 @@ template <int R, typename T, bool MULTI>
 __global__ __launch_bounds__(kWave) void k_pair_one(PairArgs a, int64_t p) {
     using V2 = typename Pair2<T>::type;
     __shared__ V2 tab[kTabRows * kTabW];
+    __shared__ int colcnt_s[kMaxSeqLen];
     const V2* gtab = reinterpret_cast<const V2*>(a.tab);
     for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
     __syncthreads();
@@ -792,7 +869,7 @@ __global__ __launch_bounds__(kWave) void k_pair_one(PairArgs a, int64_t p) {
     Coef<T> k;
     k.tau = (T)c.tau; k.eps1 = (T)c.eps1; k.eps2 = (T)c.eps2; k.c1 = (T)c.c1; k.c2 = (T)c.c2;
     k.u = (T)c.u; k.o = (T)c.o;
-    process_pair<R, T, MULTI>(a, lane, a.scratch, tab, k, p);
+    process_pair<R, T, MULTI>(a, lane, a.scratch, tab, k, p, colcnt_s);
 }
 
 // ======================================================= checkpointed form
@@ -1111,7 +1188,7 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
                             const BwdBnd<float>* __restrict__ bin, BwdBnd<float>* __restrict__ bout, float invZH,
                             float invZP, int ezH, int ezP, float thresh, int cap, int4* __restrict__ hitlog,
                             int& nlog, int32_t* __restrict__ rowcnt, int* __restrict__ flags, double& a11,
-                            bool rt_first, bool rt_last) {
+                            bool rt_first, bool rt_last, bool trp, int* __restrict__ colcnt, int log_cap) {
     const bool FIRST = band_is(FM, rt_first), LAST = band_is(LM, rt_last);
     const bool used = lane < L;
     int xo[R];
@@ -1189,7 +1266,7 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
             rU1 = qldexp(rU1, dH); rU2 = qldexp(rU2, dH); rT = qldexp(rT, dH);
             rgU = qldexp(rgU, dP); rgT = qldexp(rgT, dP);
         }
-        int kbits = 0;  // rows of this step whose hit goes to the log
+        int hbits = 0;  // rows of this step with a hit
         float pv[R];
         {
             float dU1 = rU1, dU2 = rU2, dgU = rgU;
@@ -1218,7 +1295,7 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
                 const bool hit = active && inrow[r] && P >= thresh;
                 pv[r] = P;
                 cnt[r] += hit ? 1 : 0;
-                kbits |= hit && cnt[r] <= cap ? (1 << r) : 0;
+                hbits |= hit ? (1 << r) : 0;
                 dgT = Tp[r]; dggT = gTp[r]; dgA = A[r];
                 Tp[r] = nT; gTp[r] = ngT; A[r] = nA;
                 bV1[r] = nV1; bV2[r] = nV2; gbV[r] = ngV;
@@ -1232,20 +1309,7 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
                 bout[j] = b;
             }
         }
-        if (__ballot(kbits != 0)) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const bool keep = ((kbits >> r) & 1) != 0;
-                const unsigned long long km = __ballot(keep);
-                if (km) {
-                    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0));
-                    if (keep)
-                        hitlog[nlog + rank] = make_int4(r0 + lane * R + r, cnt[r] - 1, j - 1, __float_as_int(pv[r]));
-                    nlog = __builtin_amdgcn_readfirstlane(nlog + __popcll(km));
-                }
-            }
-        }
+        log_hits<R>(hbits, trp, colcnt, cnt, cap, j, r0, lane, pv, hitlog, nlog, log_cap, flags);
         bT = rT;
         bgT = rgT;
         bA = rA;
@@ -1299,7 +1363,7 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = lane * R + r;
-        if (inrow[r]) {
+        if (!trp && inrow[r]) {
             int c = cnt[r];
             if (c > cap) {
                 atomicOr(flags, 2);
@@ -1313,13 +1377,13 @@ __device__ void ck_bwd_band(int lane, const uint8_t* __restrict__ x, const uint8
 
 template <int R, bool MULTI>
 __device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, char* slot, const float2* tab, uint8_t* yreg,
-                                const Coef<float>& k, int64_t p) {
-    const int pi = __builtin_amdgcn_readfirstlane(a.pair_i[p]);
-    const int pj = __builtin_amdgcn_readfirstlane(a.pair_j[p]);
-    const int m = __builtin_amdgcn_readfirstlane(a.lens[pi]);
-    const int n = __builtin_amdgcn_readfirstlane(a.lens[pj]);
-    const uint8_t* x = a.seqs + uniform64(a.seq_off[pi]);
-    const uint8_t* y = a.seqs + uniform64(a.seq_off[pj]);
+                                const Coef<float>& k, int64_t p, int* __restrict__ colcnt) {
+    const PairSeqs ps = pair_seqs(a, p);
+    const bool trp = ps.trp;
+    const int m = __builtin_amdgcn_readfirstlane(a.lens[ps.xi]);
+    const int n = __builtin_amdgcn_readfirstlane(a.lens[ps.yi]);
+    const uint8_t* x = a.seqs + uniform64(a.seq_off[ps.xi]);
+    const uint8_t* y = a.seqs + uniform64(a.seq_off[ps.yi]);
     const int H = kWave * R;
     const int nb = MULTI ? (m + H - 1) / H : 1;
     // the column sequence into this wave's LDS region, zeros around it (the
@@ -1334,6 +1398,7 @@ __device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, cha
     FwdBnd<float>* fb = reinterpret_cast<FwdBnd<float>*>(slot + a.off_fb);
     BwdBnd<float>* bb = reinterpret_cast<BwdBnd<float>*>(slot + a.off_bb);
     int4* hitlog = reinterpret_cast<int4*>(slot + a.off_log);
+    const int log_cap = (int)((a.slot_bytes - a.off_log) / (int64_t)sizeof(int4));
     int nlog = 0;
     float zH = 1.f, zP = 1.f;
     int ezH = 0, ezP = 0;
@@ -1358,6 +1423,8 @@ __device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, cha
     const float invZP = (float)(1.0 - a.consts->w_hmm) / zP;
     int32_t* rp = a.row_ptr + a.row_off[p];
     double a11 = 0.0;
+    const int ocap = out_row_cap(a, trp, m);
+    if (trp) zero_col_counts(lane, n, colcnt);
     for (int b = nb - 1; b >= 0; --b) {
         const int r0 = b * H;
         const int rows = min(H, m - r0);
@@ -1368,20 +1435,22 @@ __device__ __forceinline__ void process_pair_ck(const PairArgs& a, int lane, cha
         BwdBnd<float>* bo = bb + (int64_t)(b & 1) * a.bnd_stride;
         if (!MULTI)
             ck_bwd_band<R, 1, 1>(lane, x, ys, n, r0, rows, L, tab, k, c, fi, bi, bo, invZH, invZP, ezH, ezP, a.thresh,
-                                 a.cap, hitlog, nlog, rp + 1, a.flags, a11, true, true);
+                                 ocap, hitlog, nlog, rp + 1, a.flags, a11, true, true, trp, colcnt, log_cap);
         else
             ck_bwd_band<R, kBandRuntime, kBandRuntime>(lane, x, ys, n, r0, rows, L, tab, k, c, fi, bi, bo, invZH,
-                                                       invZP, ezH, ezP, a.thresh, a.cap, hitlog, nlog, rp + 1,
-                                                       a.flags, a11, b == 0, b == nb - 1);
+                                                       invZP, ezH, ezP, a.thresh, ocap, hitlog, nlog, rp + 1,
+                                                       a.flags, a11, b == 0, b == nb - 1, trp, colcnt, log_cap);
         __threadfence_block();
     }
-    finish_pair(a, lane, p, m, n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
+    if (trp) col_counts_to_rows(a, lane, n, ocap, colcnt, rp + 1);
+    finish_pair(a, lane, p, trp ? n : m, trp ? m : n, rp, hitlog, nlog, (double)zH, ezH, (double)zP, ezP, a11);
 }
 
 template <int R, bool MULTI>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs_ck(PairArgs a) {
     __shared__ float2 tab[kTabRows * kTabW];
     __shared__ uint8_t ysh[kWavesPerBlock * kYStride];
+    __shared__ int colcnt_s[kWavesPerBlock * kMaxSeqLen];  // output row counts of a transposed pair
     const float2* gtab = reinterpret_cast<const float2*>(a.tab);
     for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
     __syncthreads();
@@ -1402,7 +1471,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs_ck(PairArgs a)
         q = __builtin_amdgcn_readfirstlane(q) + seg_begin;
         if (q >= seg_end) break;
         const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
-        process_pair_ck<R, MULTI>(a, lane, slot, tab, ysh + (threadIdx.x >> 6) * kYStride, k, p);
+        process_pair_ck<R, MULTI>(a, lane, slot, tab, ysh + (threadIdx.x >> 6) * kYStride, k, p,
+                                  colcnt_s + (threadIdx.x >> 6) * kMaxSeqLen);
     }
 }
 
@@ -1410,6 +1480,7 @@ template <int R, bool MULTI>
 __global__ __launch_bounds__(kWave) void k_pair_one_ck(PairArgs a, int64_t p) {
     __shared__ float2 tab[kTabRows * kTabW];
     __shared__ uint8_t ysh[kYStride];
+    __shared__ int colcnt_s[kMaxSeqLen];
     const float2* gtab = reinterpret_cast<const float2*>(a.tab);
     for (int t = threadIdx.x; t < kTabRows * kTabW; t += blockDim.x) tab[t] = gtab[t];
     __syncthreads();
@@ -1418,7 +1489,7 @@ __global__ __launch_bounds__(kWave) void k_pair_one_ck(PairArgs a, int64_t p) {
     Coef<float> k;
     k.tau = (float)c.tau; k.eps1 = (float)c.eps1; k.eps2 = (float)c.eps2; k.c1 = (float)c.c1; k.c2 = (float)c.c2;
     k.u = (float)c.u; k.o = (float)c.o;
-    process_pair_ck<R, MULTI>(a, lane, a.scratch, tab, ysh, k, p);
+    process_pair_ck<R, MULTI>(a, lane, a.scratch, tab, ysh, k, p, colcnt_s);
 }
 
 // ------------------------------------------------------ tables (a2 step)
@@ -1533,7 +1604,8 @@ __global__ void k_stage_seqs(int32_t n, int32_t alphabet, const uint8_t* __restr
 }
 
 __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32_t* __restrict__ list_i,
-                        const int32_t* __restrict__ list_j, int64_t P, int32_t* __restrict__ pi,
+                        const int32_t* __restrict__ list_j, const uint8_t* __restrict__ tr, int64_t P,
+                        int32_t* __restrict__ pi,
                         int32_t* __restrict__ pj, int64_t* __restrict__ rows1, int32_t* __restrict__ key,
                         int* __restrict__ hist, int64_t* __restrict__ pair_nnz, ClassMap map) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1560,10 +1632,11 @@ __global__ void k_setup(int32_t n, const int32_t* __restrict__ lens, const int32
         pi[p] = (int32_t)i;
         pj[p] = (int32_t)j;
         const int64_t m = lens[i], c = lens[j];
-        rows1[p] = m + 1;
+        rows1[p] = m + 1;  // output rows: the first sequence's
         int cb = (int)(log2((double)(m * c)) * 2.0);
         cb = cb < 0 ? 0 : (cb >= kCostBins ? kCostBins - 1 : cb);
-        kk = pair_class((int)m, map) * kCostBins + cb;
+        // the class follows the rows the pair is swept with
+        kk = pair_class((int)(tr && tr[p] ? c : m), map) * kCostBins + cb;
         key[p] = kk;
     }
     wave_count_add(hist, kk, p < P);
@@ -1674,12 +1747,13 @@ hipError_t launch_reset(int* ints, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j, int64_t P,
+hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j,
+                        const uint8_t* tr, int64_t P,
                         int32_t* pi, int32_t* pj, int64_t* rows1, int32_t* key, int* hist, int64_t* pair_nnz,
                         const ClassMap& map, hipStream_t s) {
     const int64_t blocks = (P + 255) / 256;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, n, lens, list_i, list_j,
-                       P, pi, pj, rows1, key, hist, pair_nnz, map);
+                       tr, P, pi, pj, rows1, key, hist, pair_nnz, map);
     return hipGetLastError();
 }
 

@@ -79,6 +79,7 @@ struct PairArgs {
     const int32_t* pair_i;
     const int32_t* pair_j;
     const int32_t* queue;       // pair ids in processing order (class-major)
+    const uint8_t* tr;          // per pair: 1 = swept with the second sequence as rows (null: none)
     int64_t n_pairs;
     int* queue_head;            // [kClasses] per-class queue heads
     const int* hist;            // [kKeyBins] pairs per queue key
@@ -88,7 +89,9 @@ struct PairArgs {
     const void* col0;           // per row: D(i,0) of both models
     const DevConsts* consts;
     float thresh;
-    int cap;                    // staging entries per row
+    int cap;                    // staging entries per row (the class's widest rows)
+    int cap_thresh;             // floor(1 / thresh) + 1, at most kMaxSeqLen + 1: entries per output row of
+                                // a transposed pair are at most min(its rows, cap_thresh)
     // outputs
     const int64_t* row_off;
     int32_t* row_ptr;
@@ -120,8 +123,8 @@ hipError_t launch_tables(const DevParams* p, void* tab, DevConsts* c, void* col0
 size_t col0_bytes();
 hipError_t launch_reset(int* ints, int n_ints, hipStream_t s);
 hipError_t launch_setup(int32_t n, const int32_t* lens, const int32_t* list_i, const int32_t* list_j,
-                        int64_t n_pairs, int32_t* pair_i, int32_t* pair_j, int64_t* rows1, int32_t* key,
-                        int* hist, int64_t* pair_nnz, const ClassMap& map, hipStream_t s);
+                        const uint8_t* tr, int64_t n_pairs, int32_t* pair_i, int32_t* pair_j, int64_t* rows1,
+                        int32_t* key, int* hist, int64_t* pair_nnz, const ClassMap& map, hipStream_t s);
 hipError_t launch_bins(const int* hist, int* bin_start, hipStream_t s);
 hipError_t launch_fill_queue(int64_t n_pairs, const int32_t* key, const int* bin_start, int* bin_fill,
                              int32_t* queue, hipStream_t s);

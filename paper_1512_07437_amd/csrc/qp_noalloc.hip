@@ -256,6 +256,7 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
     a.col0 = d_col0;
     a.consts = d_consts;
     a.thresh = thresh;
+    a.cap_thresh = (int)std::min<double>(qp::kMaxSeqLen + 1, std::floor(1.0 / (double)thresh) + 1.0);
     a.row_off = out->row_off;
     a.row_ptr = out->row_ptr;
     a.pair_nnz = out->nnz_off;
@@ -297,7 +298,7 @@ extern "C" qp_status qp_posteriors_noalloc(const uint8_t* d_seqs, const int64_t*
     NA_TRY(qp::launch_stage_seqs(n, qp::alphabet_of(params), d_seqs, d_seq_off, d_lens, d_seqa_off, d_seqa,
                                  d_ints + kIntFlags, s));
     NA_TRY(qp::launch_tables(d_params, d_tab, d_consts, d_col0, mmax, fp64, s));
-    NA_TRY(qp::launch_setup(n, d_lens, nullptr, nullptr, P, out->pair_i, out->pair_j, out->row_off, d_key,
+    NA_TRY(qp::launch_setup(n, d_lens, nullptr, nullptr, nullptr, P, out->pair_i, out->pair_j, out->row_off, d_key,
                             d_ints + kIntHist, out->nnz_off, cmap, s));
     NA_TRY(qp::launch_bins(d_ints + kIntHist, d_bin_start, s));
     NA_TRY(qp::launch_fill_queue(P, d_key, d_bin_start, d_ints + kIntFill, d_queue, s));

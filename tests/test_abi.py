@@ -41,7 +41,7 @@ def test_struct_layout(B):
     assert ctypes.sizeof(B.qp_params) == 8 * 400 + 8 + 8 * 4 + 8 * 400 + 8 * 4 + 8
     assert ctypes.sizeof(B.qp_result) == 4 + 4 + 8 * 3 + 8 * 9 + 8 + 8
     assert ctypes.sizeof(B.qp_request_times) == 8 * 6
-    assert ctypes.sizeof(B.qp_tuning) == 4 * 8 + 8 * 9 + 4 * 9 + 4  # concurrent_classes (no trailing pad)
+    assert ctypes.sizeof(B.qp_tuning) == 4 * 8 + 8 * 9 + 4 * 9 + 4 + 4 + 4  # concurrent_classes, orient, pad to 8
     assert ctypes.sizeof(B.qp_noalloc_out) == 8 * 11
     assert [f[0] for f in B.qp_noalloc_out._fields_ if f[0] != "capacity"] == list(B.NOALLOC_OUT_FIELDS)
 
@@ -173,16 +173,22 @@ def test_tuning_table(B):
         B.set_tuning()
         d = B.get_tuning()
         assert d["rows_per_lane"] == list(range(1, 9)) and d["waves_frac"] == [1.0] * 9
-        assert d["recompute"] == [0, 0, 1, 1, 1, 0, 0, 0, 0] and d["concurrent_classes"] == 1
+        assert d["recompute"] == [0, 0, 1, 1, 1, 0, 0, 0, 0] and d["concurrent_classes"] == 1 and d["orient"] == 1
         B.set_tuning(concurrent_classes=0)
         assert B.get_tuning()["concurrent_classes"] == 0
         t = B.get_tuning()
         with pytest.raises(B.QpError) as e:
             B.set_tuning(concurrent_classes=2)
         assert e.value.status == B.QP_EINVAL and B.get_tuning() == t
+        B.set_tuning(orient=0)
+        assert B.get_tuning()["orient"] == 0
+        t = B.get_tuning()
+        with pytest.raises(B.QpError) as e:
+            B.set_tuning(orient=3)
+        assert e.value.status == B.QP_EINVAL and B.get_tuning() == t
     finally:
         B.set_tuning(before["rows_per_lane"], before["waves_frac"], before["recompute"],
-                     before["concurrent_classes"])
+                     before["concurrent_classes"], before["orient"])
 
 
 def test_tuning_file_is_valid(B):

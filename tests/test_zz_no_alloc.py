@@ -58,10 +58,18 @@ def _run_noalloc(torch, B, fam, params, thresh, t, cap, stream):
 
 
 def _plan_result(B, fam, params, thresh):
+    """The plan form's outputs, every pair swept with its first sequence as
+    rows (the allocation-free entry point never transposes a pair), so the
+    two run the same arithmetic."""
     d_seqs, d_off = B.device_inputs(fam, "cuda:0")
     import torch
     lens = [len(s) for s in fam]
-    plan = B.Plan(lens, params, thresh, nnz_capacity=-1)
+    orient = B.get_tuning()["orient"]
+    B.set_tuning(orient=0)
+    try:
+        plan = B.Plan(lens, params, thresh, nnz_capacity=-1)
+    finally:
+        B.set_tuning(orient=orient)
     s = torch.cuda.current_stream()
     plan.run(d_seqs.data_ptr(), d_off.data_ptr(), s.cuda_stream)
     res = plan.download()
