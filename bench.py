@@ -326,9 +326,10 @@ def main():
                     help="skip the selective-consistency timing on the C2 family after the timed region")
     ap.add_argument("--no-alone", action="store_true",
                     help="skip the pass that times the dominant kernel with the device to itself")
-    ap.add_argument("--recompute", default="table", choices=["table", "none", "all"],
-                    help="FP32 pair-kernel form per class: the tuning table's choice, the spilling form for "
-                         "every class (none) or the checkpointed form for every class (all)")
+    ap.add_argument("--recompute", default="table",
+                    help="FP32 pair-kernel form per class: the tuning table's choice (table), the spilling form "
+                         "for every class (none), the checkpointed form wherever it exists (all), or nine "
+                         "comma-separated 0/1 flags (the tuning table's recompute entries)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the posterior engine runs one process on one MI355X "
@@ -344,8 +345,15 @@ def main():
     from paper_1512_07437_amd import binding as B
     from paper_1512_07437_amd import workload as W
 
-    if args.recompute != "table":
-        B.set_tuning(recompute=[1, 1, 1, 1, 1, 0, 0, 0, 1] if args.recompute == "all" else [0] * 9)
+    if args.recompute == "all":
+        B.set_tuning(recompute=[1, 1, 1, 1, 1, 0, 0, 0, 1])
+    elif args.recompute == "none":
+        B.set_tuning(recompute=[0] * 9)
+    elif args.recompute != "table":
+        flags = [int(v) for v in args.recompute.split(",")]
+        if len(flags) != 9:
+            raise SystemExit("--recompute takes table, none, all or nine comma-separated flags")
+        B.set_tuning(recompute=flags)
     if args.classes != "table":
         B.set_tuning(concurrent_classes=int(args.classes == "concurrent"))
     if args.orient != "table":
