@@ -92,6 +92,7 @@ def consistency_extra(B, W, params, thresh: float, say, reps: int = 3, tree_thre
         tdist = B.tree_distance(joins, k)
         d_t = torch.from_numpy(tdist).to("cuda:0")
         passes = 2 if k < 50 else 1
+        pair_bytes = np.diff(host["nnz_off"]) * 8 + (np.array([lens[i] for i in host["pair_i"]]) + 1) * 4
         rx = B.Relax(lens, tree_threshold, amplification, passes, thresh, in_capacity=int(dres.nnz))
         try:
             rx.run(dres, int(dres.nnz), d_t.data_ptr(), s.cuda_stream)
@@ -114,15 +115,64 @@ def consistency_extra(B, W, params, thresh: float, say, reps: int = 3, tree_thre
     D[iu] = tdist
     D = D + D.T
     M = (D <= tree_threshold) & ~np.eye(k, dtype=bool)
-    sel = (M.astype(np.int64) @ M.T.astype(np.int64))[iu]
+    Mi = M.astype(np.int64)
+    sel = (Mi @ Mi.T)[iu]
     n_pairs = k * (k - 1) // 2
+    # algorithmic bytes of a pass: every pair reads, for each selected z, the
+    # matrices S_xz and S_zy once (CSR entries and row pointers), and writes
+    # its relaxed matrix
+    PB = np.zeros((k, k))
+    PB[iu] = pair_bytes
+    PB = PB + PB.T
+    MB = Mi * PB
+    read = float(((MB @ Mi.T) + (Mi @ MB.T))[iu].sum() + pair_bytes.sum())
+    written = float(int(out.nnz) * 8 + (np.array(lens)[iu[0]] + 1).sum() * 4)
+    achieved = (read + written) / (ms * 1e-3) / 1e9
     r = {"workload": "C2: 200 seqs, L ~ U{250..350}, %d pairs" % n_pairs, "tree_threshold": tree_threshold,
          "amplification": amplification, "passes": passes, "ms": round(ms, 3),
          "pairs_per_s": round(n_pairs / (ms * 1e-3), 1), "entries_in": int(dres.nnz), "entries_out": int(out.nnz),
+         "z_terms_per_s": round(float(sel.sum()) / (ms * 1e-3), 1),
          "third_sequences_per_pair_mean": round(float(sel.mean()), 2), "device_bytes": relax_bytes,
-         "where": "after the timed region, HIP events on the run stream"}
+         "where": "after the timed region, HIP events on the run stream",
+         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                      "frac": round(achieved / 8000.0, 4), "algorithmic_bytes": round(read + written),
+                      "what": "per pass: each pair's own matrix and, for each selected z, S_xz and S_zy read "
+                              "once (CSR entries and row pointers), the relaxed matrices written"}}
     say("consistency on C2: %s" % r)
     return r
+
+
+def consistency_cpu_baseline(W, params, thresh: float, tree_threshold: int = 200, amplification: float = 3.0,
+                             k_sample: int = 12):
+    """The FP64 oracle's relaxation (dense matrices, one pass) timed on one
+    core on a bounded sample of the C2 family: its first k_sample sequences,
+    their oracle posteriors and the oracle's guide tree as input.  Rate in
+    relaxation terms (pair x selected third sequence) per second, the unit of
+    the device figure's z_terms_per_s."""
+    import oracle
+    from oracle import consistency as OC
+    from oracle import tree as OT
+    fam = W.c2_family()[:k_sample]
+    k = len(fam)
+    S0, dist = {}, []
+    for x in range(k):
+        for y in range(x + 1, k):
+            r = oracle.pair(fam[x], fam[y], params, per_model=False)
+            post = r["post"].copy()
+            post[post < thresh] = 0.0
+            S0[(x, y)] = post
+            dist.append(1.0 - r["ea"])
+    joins, _ = OT.wpgma(dist, k)
+    tdist = OT.tree_distance(joins, k)
+    terms = sum(len(OC.selected(tdist, k, x, y, tree_threshold)) for x in range(k) for y in range(x + 1, k))
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # the matrix products on one thread
+        t0 = time.perf_counter()
+        OC.relax_pass(S0, k, tdist, tree_threshold, amplification, thresh)
+        dt = time.perf_counter() - t0
+    return {"value": round(terms / dt, 1), "unit": "z-terms/s", "cores": 1, "kind": "oracle",
+            "sample": "one pass over the first %d C2 sequences (%d pairs, %d terms, %.2f s), oracle posteriors "
+                      "and guide tree as input" % (k, k * (k - 1) // 2, terms, dt)}
 
 
 def committed_traffic(kernel: str, workload_key: str):
@@ -549,6 +599,9 @@ def main():
     del res
     if args.workload in ("c2", "c3") and not args.no_consistency and prec == B.QP_FP32_SCALED:
         out.setdefault("extra", {})["consistency"] = consistency_extra(B, W, params, args.thresh, say)
+        if not args.no_cpu:
+            out["extra"]["consistency"]["cpu_baseline"] = consistency_cpu_baseline(W, mp, args.thresh)
+            say("consistency cpu baseline: %s" % out["extra"]["consistency"]["cpu_baseline"])
     if args.workload == "c3" and args.c4_families > 0 and prec == B.QP_FP32_SCALED:
         # the metric's latency term: the C4 stream through the serving loop
         c4 = serve_stream(args, say, args.c4_families)
