@@ -307,7 +307,7 @@ qp_status qp_plan_set_per_pair(qp_plan* plan, int32_t on);
  * per lane) (QP_EINVAL for recompute[c] = 1 on classes 5..7);
  * the FP64 path always uses the other form.
  * Default: rows_per_lane[r-1] = r, waves_frac = 1, recompute = 1 for the
- * classes of 3 to 5 rows per lane (the banded class is faster spilling).
+ * classes of 1 to 5 rows per lane (the banded classes are faster spilling).
  * concurrent_classes = 1 runs a plan's kernel classes side by side on forked
  * streams (one class's tail overlaps the next one's work); 0 runs them one
  * after another on the run stream, largest rows per lane first, each with

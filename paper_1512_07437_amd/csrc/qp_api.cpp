@@ -29,7 +29,7 @@ void default_tuning(qp_tuning* t) {
     for (int r = 0; r < 8; ++r) t->rows_per_lane[r] = r + 1;
     for (int c = 0; c < 9; ++c) {
         t->waves_frac[c] = 1.0;
-        t->recompute[c] = c >= 2 && c <= 4 ? 1 : 0;
+        t->recompute[c] = c <= qp::kCkMaxClass ? 1 : 0;
     }
     t->concurrent_classes = 1;
     t->orient = 1;

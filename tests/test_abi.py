@@ -173,7 +173,7 @@ def test_tuning_table(B):
         B.set_tuning()
         d = B.get_tuning()
         assert d["rows_per_lane"] == list(range(1, 9)) and d["waves_frac"] == [1.0] * 9
-        assert d["recompute"] == [0, 0, 1, 1, 1, 0, 0, 0, 0] and d["concurrent_classes"] == 1 and d["orient"] == 1
+        assert d["recompute"] == [1, 1, 1, 1, 1, 0, 0, 0, 0] and d["concurrent_classes"] == 1 and d["orient"] == 1
         B.set_tuning(concurrent_classes=0)
         assert B.get_tuning()["concurrent_classes"] == 0
         t = B.get_tuning()
