@@ -6,8 +6,12 @@
 // Layout of one pair on one wavefront
 // -----------------------------------
 // Rows (residues of x) are striped over the 64 lanes: lane l owns rows
-// l*R .. l*R+R-1 of a band of 64*R rows; longer x is cut into bands processed
-// one after the other.  Columns (residues of y) are swept in a skewed
+// l*R .. l*R+R-1 of a band of 64*R rows; an x longer than 512 is cut into
+// ceil(m/512) bands of R = ceil(m / (64 * bands)) rows per lane, processed
+// one after the other (each R its own kernel class).  x is the pair's first
+// sequence, or its second when the host finds the transposed sweep cheaper
+// (the models are symmetric, so P(y, x) = P(x, y)^T; such a pair's output
+// rows are the sweep's columns).  Columns (residues of y) are swept in a skewed
 // wavefront: at step s lane l handles column j = s - l + 1, so the row above
 // its strip (lane l-1) finished column j one step earlier and hands its last
 // row over with one DPP wave shift.  The backward pass runs the same skew in
@@ -20,10 +24,12 @@
 // rounding from the scaling itself.
 //
 // Posteriors need the forward match value at the same cell as the backward
-// one; the forward pass stores (f_hmm, f_pf) per cell, step-major and lane-
-// contiguous, so both the store and the reversed read are fully coalesced.
-// The backward pass fuses the posterior, the average of the two models, the
-// threshold, the per-row staging of CSR entries and the reverse MEA recursion.
+// one.  The spilling form stores (f_hmm, f_pf) per cell, step-major and lane-
+// contiguous, so both the store and the reversed read are fully coalesced;
+// the checkpointed form saves the forward state every 8 steps and recomputes
+// each block in registers during the backward sweep.  The backward pass
+// fuses the posterior, the average of the two models, the threshold, the
+// hit log of CSR entries and the reverse MEA recursion.
 #include <hip/hip_runtime.h>
 
 #include <climits>
