@@ -144,6 +144,23 @@ def test_relax_c2_subfamily(B, params):
     _say("C2 sub-family: %d entries, max |d| %.3g" % (res["nnz"], worst))
 
 
+def test_relax_more_thirds_than_a_wave(B, params):
+    """72 short sequences, every third sequence selected: 70 z's per pair,
+    more than a wave has lanes (64), and every pair's z list longer than the
+    other cases'."""
+    import torch
+    thresh, h = 0.01, 3.0
+    rng = np.random.default_rng(70)
+    fam = W.make_family(72, rng.integers(24, 41, size=72), np.random.SeedSequence(70))
+    S0, tdist, arrays = _oracle_stage1(fam, params, thresh)
+    T = int(tdist.max())
+    _say("72-sequence relaxation: T=%d" % T)
+    res = _gpu_relax(B, torch, fam, arrays, tdist, T, h, 1, thresh)
+    S_or = OC.consistency(S0, len(fam), tdist, T, h, 1, thresh)
+    worst = _compare(B, res, fam, S_or, thresh)
+    _say("72-sequence relaxation: %d entries, max |d| %.3g" % (res["nnz"], worst))
+
+
 def test_relax_empty_selection_keeps_input(B, params):
     """T below every tree-guided distance: no relaxation, each matrix is its
     input (h_xy = 1, S' = 2 S / 2)."""
