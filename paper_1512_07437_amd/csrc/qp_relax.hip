@@ -37,6 +37,7 @@ namespace {
 using qp::kWave;
 constexpr int kRelaxWaves = 4;       // wavefronts per block
 constexpr int kMaxRelaxSeqs = 2048;  // a selected sequence is an int16 in the LDS list
+constexpr int kRelaxGroup = 8;          // S_xz entries of one row taken together
 constexpr int64_t kRelaxLds = 64 * 1024;  // dynamic LDS of a k_relax block
 
 struct Csr {
@@ -203,13 +204,40 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
                 const int64_t bb = in.nnz_off[pzy];
                 float* accr = acc + r * acc_stride;
                 const int ea1 = ra[i + 1];
-                for (int ea = ra[i]; ea < ea1; ++ea) {
-                    const int kk = ca[ba + ea];
-                    const float v1 = va[ba + ea];
-                    const int eb1 = rb[kk + 1];
-                    for (int eb = rb[kk]; eb < eb1; ++eb) {
-                        const int j = cb[bb + eb];
-                        if (j >= 0 && j < n) atomicAdd(&accr[j], v1 * vb[bb + eb]);
+                // up to kRelaxGroup entries of row i at a time: their columns,
+                // then the row ranges of S_zy they select, then those rows
+                // walked side by side, so each round has a group's loads in
+                // flight instead of one chain of dependent loads per entry
+                for (int eg = ra[i]; eg < ea1; eg += kRelaxGroup) {
+                    int kk[kRelaxGroup], lo[kRelaxGroup], len[kRelaxGroup];
+                    float v1[kRelaxGroup];
+#pragma unroll
+                    for (int u = 0; u < kRelaxGroup; ++u) {
+                        const int e = eg + u < ea1 ? eg + u : eg;  // a stored entry either way
+                        kk[u] = ca[ba + e];
+                        v1[u] = va[ba + e];
+                    }
+                    int rounds = 0;
+#pragma unroll
+                    for (int u = 0; u < kRelaxGroup; ++u) {
+                        lo[u] = rb[kk[u]];
+                        len[u] = eg + u < ea1 ? rb[kk[u] + 1] - lo[u] : 0;
+                        rounds = max(rounds, len[u]);
+                    }
+                    for (int t = 0; t < rounds; ++t) {
+                        int jj[kRelaxGroup];
+                        float ww[kRelaxGroup];
+#pragma unroll
+                        for (int u = 0; u < kRelaxGroup; ++u) {
+                            const bool ok = t < len[u];
+                            // past its row: entry eg of S_xz, stored in every entry array
+                            const int64_t eb = ok ? bb + lo[u] + t : ba + eg;
+                            jj[u] = ok ? cb[eb] : -1;
+                            ww[u] = vb[eb];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kRelaxGroup; ++u)
+                            if (jj[u] >= 0 && jj[u] < n) atomicAdd(&accr[jj[u]], v1[u] * ww[u]);
                     }
                 }
             }
