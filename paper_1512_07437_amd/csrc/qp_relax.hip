@@ -38,6 +38,7 @@ using qp::kWave;
 constexpr int kRelaxWaves = 4;       // wavefronts per block
 constexpr int kMaxRelaxSeqs = 2048;  // a selected sequence is an int16 in the LDS list
 constexpr int kRelaxGroup = 8;          // S_xz entries of one row taken together
+constexpr int kQueueSlot = 8;           // flags[8 + pass]: the pair counter of each pass (at most 8 passes)
 constexpr int64_t kRelaxLds = 64 * 1024;  // dynamic LDS of a k_relax block
 
 struct Csr {
@@ -130,14 +131,23 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
     const int32_t* __restrict__ tdist, int32_t T, float h, float thresh, int32_t cap,
     const int64_t* __restrict__ out_row_off, int32_t* __restrict__ out_row_ptr, const int64_t* __restrict__ stage_off,
     int32_t* __restrict__ stage_col, float* __restrict__ stage_val, int64_t* __restrict__ out_nnz,
-    int* __restrict__ flags, int32_t B, int32_t acc_stride) {
+    int* __restrict__ flags, int* __restrict__ queue, int32_t B, int32_t acc_stride) {
     // dynamic LDS: [kRelaxWaves][B][acc_stride] accumulators, then
     // [kRelaxWaves][k] selected third sequences
     extern __shared__ float lds[];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     float* acc = lds + (int64_t)w * B * acc_stride;
     int16_t* zl = reinterpret_cast<int16_t*>(lds + (int64_t)kRelaxWaves * B * acc_stride) + (int64_t)w * k;
-    for (int64_t p = (int64_t)blockIdx.x * kRelaxWaves + w; p < P; p += (int64_t)gridDim.x * kRelaxWaves) {
+    // each wavefront takes the next pair from the pass's counter (zero at the
+    // start of the run) until none is left: the number of third sequences,
+    // and so a pair's work, varies widely from pair to pair.  Every lane
+    // takes part in the atomic (lane 0 adds one, the others nothing), so no
+    // branch on the lane index comes before the wave-wide read of its result
+    // that the compiler could route some lanes around.
+    for (;;) {
+        const int next = atomicAdd(queue, lane == 0 ? 1 : 0);
+        const int64_t p = __builtin_amdgcn_readfirstlane(next);
+        if (p >= P) break;
         const int x = __builtin_amdgcn_readfirstlane(pair_i[p]);
         const int y = __builtin_amdgcn_readfirstlane(pair_j[p]);
         const int m = lens[x], n = lens[y];
@@ -500,7 +510,7 @@ qp_status qp_relax_run(qp_relax* r, const qp_device_result* in, int64_t in_nnz, 
                            r->d_lens, r->d_pi, r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col,
                            r->d_tr_val, d_tdist, r->T, (float)r->h, r->thresh, r->cap, r->d_row_off,
                            r->d_out_row_ptr[q], r->d_stage_off, r->d_stage_col, r->d_stage_val, r->d_out_nnz[q],
-                           r->d_flags, r->rows_per_block, r->acc_stride);
+                           r->d_flags, r->d_flags + kQueueSlot + pass, r->rows_per_block, r->acc_stride);
         RX_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(r->d_out_nnz[q] + r->P), 2);
         RX_TRY(hipGetLastError());
