@@ -666,9 +666,12 @@ __device__ void finish_pair(const PairArgs& a, int lane, int64_t p, int m, int n
     if (lane == 0) rp[0] = 0;
     __threadfence_block();
     const int nnz = carry;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(a.pool_head, (unsigned long long)nnz);
-    base = __shfl(base, 0, kWave);
+    // every lane takes part in the atomic (lane 0 adds the pair's entries),
+    // so the wave-wide read of lane 0's result follows no branch on the lane
+    const unsigned long long got = atomicAdd(a.pool_head, lane == 0 ? (unsigned long long)nnz : 0ull);
+    const unsigned long long base =
+        ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(got >> 32)) << 32) |
+        (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(got & 0xffffffffull));
     if (lane == 0) {
         a.pair_nnz[p] = nnz;
         a.pair_base[p] = (int64_t)base;
@@ -849,10 +852,11 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs(PairArgs a) {
     const int seg_end = __builtin_amdgcn_readfirstlane(a.bin_start[k0] + a.hist[k0]);
     int* head = a.queue_head + a.cls;
     for (;;) {
-        int q = 0;
-        if (lane == 0) q = atomicAdd(head, 1);
+        // every lane takes part in the atomic (lane 0 adds one, the others
+        // nothing), so no branch on the lane index comes before the wave-wide
+        // read of its result that the compiler could route some lanes around;
         // wave-uniform from here on: scalar registers and scalar branches
-        q = __builtin_amdgcn_readfirstlane(q) + seg_begin;
+        const int q = __builtin_amdgcn_readfirstlane(atomicAdd(head, lane == 0 ? 1 : 0)) + seg_begin;
         if (q >= seg_end) break;
         const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
         process_pair<R, T, MULTI>(a, lane, slot, tab, k, p, colcnt_s + (threadIdx.x >> 6) * kMaxSeqLen);
@@ -1472,9 +1476,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_pairs_ck(PairArgs a)
     const int seg_end = __builtin_amdgcn_readfirstlane(a.bin_start[k0] + a.hist[k0]);
     int* head = a.queue_head + a.cls;
     for (;;) {
-        int q = 0;
-        if (lane == 0) q = atomicAdd(head, 1);
-        q = __builtin_amdgcn_readfirstlane(q) + seg_begin;
+        // the pop as in k_pairs
+        const int q = __builtin_amdgcn_readfirstlane(atomicAdd(head, lane == 0 ? 1 : 0)) + seg_begin;
         if (q >= seg_end) break;
         const int64_t p = __builtin_amdgcn_readfirstlane(a.queue[q]);
         process_pair_ck<R, MULTI>(a, lane, slot, tab, ysh + (threadIdx.x >> 6) * kYStride, k, p,
