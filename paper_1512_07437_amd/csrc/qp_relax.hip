@@ -39,6 +39,7 @@ constexpr int kRelaxWaves = 4;       // wavefronts per block
 constexpr int kMaxRelaxSeqs = 2048;  // a selected sequence is an int16 in the LDS list
 constexpr int kRelaxGroup = 8;          // S_xz entries of one row taken together
 constexpr int kQueueSlot = 8;           // flags[8 + pass]: the pair counter of each pass (at most 8 passes)
+constexpr int kOrderBins = 64;          // cost bins of the pair order (costliest first)
 constexpr int64_t kRelaxLds = 64 * 1024;  // dynamic LDS of a k_relax block
 
 struct Csr {
@@ -131,23 +132,25 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
     const int32_t* __restrict__ tdist, int32_t T, float h, float thresh, int32_t cap,
     const int64_t* __restrict__ out_row_off, int32_t* __restrict__ out_row_ptr, const int64_t* __restrict__ stage_off,
     int32_t* __restrict__ stage_col, float* __restrict__ stage_val, int64_t* __restrict__ out_nnz,
-    int* __restrict__ flags, int* __restrict__ queue, int32_t B, int32_t acc_stride) {
+    int* __restrict__ flags, int* __restrict__ queue, const int32_t* __restrict__ order, int32_t B,
+    int32_t acc_stride) {
     // dynamic LDS: [kRelaxWaves][B][acc_stride] accumulators, then
     // [kRelaxWaves][k] selected third sequences
     extern __shared__ float lds[];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     float* acc = lds + (int64_t)w * B * acc_stride;
     int16_t* zl = reinterpret_cast<int16_t*>(lds + (int64_t)kRelaxWaves * B * acc_stride) + (int64_t)w * k;
-    // each wavefront takes the next pair from the pass's counter (zero at the
-    // start of the run) until none is left: the number of third sequences,
-    // and so a pair's work, varies widely from pair to pair.  Every lane
+    // each wavefront takes the next pair of the cost order from the pass's
+    // counter (zero at the start of the run) until none is left: the number
+    // of third sequences, and so a pair's work, varies widely from pair to
+    // pair.  Every lane
     // takes part in the atomic (lane 0 adds one, the others nothing), so no
     // branch on the lane index comes before the wave-wide read of its result
     // that the compiler could route some lanes around.
     for (;;) {
-        const int next = atomicAdd(queue, lane == 0 ? 1 : 0);
-        const int64_t p = __builtin_amdgcn_readfirstlane(next);
-        if (p >= P) break;
+        const int q = __builtin_amdgcn_readfirstlane(atomicAdd(queue, lane == 0 ? 1 : 0));
+        if (q >= P) break;
+        const int64_t p = __builtin_amdgcn_readfirstlane(order[q]);
         const int x = __builtin_amdgcn_readfirstlane(pair_i[p]);
         const int y = __builtin_amdgcn_readfirstlane(pair_j[p]);
         const int m = lens[x], n = lens[y];
@@ -282,6 +285,48 @@ __global__ __launch_bounds__(kWave * kRelaxWaves) void k_relax(
     }
 }
 
+// The order in which the wavefronts take pairs: by the pair's work, about
+// its selected third sequences times its rows, in bins a third of an octave
+// wide, the costliest bin first (pairs with nothing selected last), so that
+// no expensive pair starts when the others are nearly done.  bins holds
+// [kOrderBins] counts, [kOrderBins] first slots, [kOrderBins] fill counters.
+__global__ void k_order_keys(int32_t k, int64_t P, const int32_t* __restrict__ lens,
+                             const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j,
+                             const int32_t* __restrict__ tdist, int32_t T, int32_t* __restrict__ key,
+                             int* __restrict__ bins) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int x = pair_i[p], y = pair_j[p];
+    int nsel = 0;
+    for (int z = 0; z < k; ++z) {
+        if (z == x || z == y) continue;
+        const int dxz = tdist[pidx(min(x, z), max(x, z), k)];
+        const int dyz = tdist[pidx(min(y, z), max(y, z), k)];
+        nsel += max(dxz, dyz) <= T ? 1 : 0;
+    }
+    const float cost = (float)nsel * (float)lens[x];
+    const int kb = nsel == 0 ? 0 : min(kOrderBins - 1, 1 + (int)(3.f * log2f(cost)));
+    key[p] = kb;
+    atomicAdd(&bins[kb], 1);
+}
+
+__global__ void k_order_starts(int* __restrict__ bins) {
+    if (threadIdx.x != 0) return;
+    int at = 0;
+    for (int b = kOrderBins - 1; b >= 0; --b) {
+        bins[kOrderBins + b] = at;
+        at += bins[b];
+    }
+}
+
+__global__ void k_order_fill(int64_t P, const int32_t* __restrict__ key, int* __restrict__ bins,
+                             int32_t* __restrict__ order) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int kb = key[p];
+    order[bins[kOrderBins + kb] + atomicAdd(&bins[2 * kOrderBins + kb], 1)] = (int32_t)p;
+}
+
 __global__ void k_zero_i32(int* __restrict__ p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -318,6 +363,9 @@ struct qp_relax {
     float* d_out_val[2] = {};
     int64_t* d_scan_tmp = nullptr;
     int* d_flags = nullptr;
+    int32_t* d_key = nullptr;    // [P] cost bin of each pair
+    int32_t* d_order = nullptr;  // [P] pairs, costliest first
+    int* d_bins = nullptr;       // [3 * kOrderBins] counts, first slots, fill counters
     hipStream_t last_stream = nullptr;
     hipEvent_t done = nullptr;
     bool ran = false;
@@ -450,6 +498,9 @@ qp_status qp_relax_create(const int32_t* lens, int32_t n, int64_t in_capacity, i
     }
     A((void**)&r->d_scan_tmp, 8 * (qp::scan_tmp_elems(P + 1) + 8));
     A((void**)&r->d_flags, 64);
+    A((void**)&r->d_key, 4 * P);
+    A((void**)&r->d_order, 4 * P);
+    A((void**)&r->d_bins, 4 * 3 * kOrderBins);
     if (as != QP_OK) {
         relax_free(r);
         delete r;
@@ -498,6 +549,18 @@ qp_status qp_relax_run(qp_relax* r, const qp_device_result* in, int64_t in_nnz, 
     }
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, r->d_flags, 16);
     RX_TRY(hipGetLastError());
+    {
+        const unsigned og = (unsigned)((r->P + 255) / 256);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, r->d_bins, 3 * kOrderBins);
+        RX_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_order_keys, dim3(og), dim3(256), 0, s, r->k, r->P, r->d_lens, r->d_pi, r->d_pj,
+                           d_tdist, r->T, r->d_key, r->d_bins);
+        RX_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_order_starts, dim3(1), dim3(64), 0, s, r->d_bins);
+        RX_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_order_fill, dim3(og), dim3(256), 0, s, r->P, r->d_key, r->d_bins, r->d_order);
+        RX_TRY(hipGetLastError());
+    }
     const int64_t waves_wanted = (r->P + kRelaxWaves - 1) / kRelaxWaves;
     const unsigned grid = (unsigned)std::min<int64_t>(waves_wanted, (int64_t)r->n_cu * 8);
     Csr cur{in->row_off, in->row_ptr, in->nnz_off, in->col, in->val};
@@ -510,7 +573,8 @@ qp_status qp_relax_run(qp_relax* r, const qp_device_result* in, int64_t in_nnz, 
                            r->d_lens, r->d_pi, r->d_pj, cur, r->d_tr_row_off, r->d_tr_row_ptr, r->d_tr_col,
                            r->d_tr_val, d_tdist, r->T, (float)r->h, r->thresh, r->cap, r->d_row_off,
                            r->d_out_row_ptr[q], r->d_stage_off, r->d_stage_col, r->d_stage_val, r->d_out_nnz[q],
-                           r->d_flags, r->d_flags + kQueueSlot + pass, r->rows_per_block, r->acc_stride);
+                           r->d_flags, r->d_flags + kQueueSlot + pass, r->d_order, r->rows_per_block,
+                           r->acc_stride);
         RX_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(r->d_out_nnz[q] + r->P), 2);
         RX_TRY(hipGetLastError());
@@ -590,6 +654,7 @@ int64_t qp_relax_device_bytes(const qp_relax* r) {
     const int64_t P = r->P;
     const int64_t tr_cap = r->passes > 1 ? std::max(r->in_cap, r->bound) : r->in_cap;
     b += 4 * (int64_t)r->k + 8 * P + 24 * (P + 1) + 4 * r->tr_rows + 8 * tr_cap + 8 * r->bound;
+    b += 8 * P + 4 * 3 * kOrderBins;  // the pair order
     b += (r->passes > 1 ? 2 : 1) * (4 * r->total_rows + 8 * (P + 1) + 8 * r->bound);
     return b;
 }
