@@ -103,6 +103,29 @@ def test_c5_precision(B, params, prec):
         _check_pair(res, k, x, y, orc, 0.01, TOL[prec])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_divergent_pairs_precision(B, params, prec):
+    """Precision under divergence at single-band lengths: 16 independent
+    pairs with the substitution (0.6) and indel (0.1) rates of the C5 study,
+    200-500 residues, against the FP64 oracle: stored values within 1e-5
+    (FP32 path) / 1e-7 (FP64 path), EA and log Z alike.  Distant sequences
+    spread each row's posterior mass thin, so many values sit near the
+    scaling floor of the FP32 sweep."""
+    ab = W.c5_pairs(n_pairs=16, seed=7, lo=200, hi=500)
+    fam = [s for pair in ab for s in pair]
+    pi = np.arange(0, 2 * len(ab), 2, dtype=np.int32)
+    _say("divergent pairs 200-500, precision", prec)
+    res = B.qp_posteriors_pairs(fam, pi, pi + 1, B.make_params(params, prec), 0.01)
+    worst = 0.0
+    for k, (x, y) in enumerate(ab):
+        orc = oracle.pair(x, y, params, per_model=False)
+        _check_pair(res, k, x, y, orc, 0.01, TOL[prec])
+        rp, col, val = B.pair_csr(res, k)
+        rows = np.repeat(np.arange(len(x)), np.diff(rp))
+        worst = max(worst, float(np.abs(val.astype(np.float64) - orc["post"][rows, col]).max(initial=0.0)))
+    _say("divergent pairs, precision %d: max |dP| %.3g" % (prec, worst))
+
+
 @pytest.mark.skip(reason="a run at threshold 1e-30 exceeded its time limit and the cause is not yet "
                          "identified; the case stays disabled until it is")
 @pytest.mark.parametrize("prec", [0, 1])
