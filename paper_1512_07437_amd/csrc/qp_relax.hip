@@ -9,15 +9,17 @@
 // amplification and the pass count; the formula is the consistency
 // transformation of the aligners the method descends from, read as above.
 //
-// Layout: the all-pairs CSR of the posterior stage (qp_device_result).  Per
-// pass: (1) every pair's matrix is transposed into a CSR of the same entry
-// range (rows = residues of the second sequence), so both orientations of
-// every S_ab are rows of some CSR; (2) one wavefront per pair accumulates
-// each output row in LDS -- lanes take the selected z's, walk row i of S_xz
-// and, for each of its entries (k, v), row k of S_zy, adding v * S_zy(k, j)
-// with LDS atomics -- then scales, thresholds and compacts the row in
-// column order; (3) per-pair counts are scanned and the entries gathered in
-// pair order.
+// Layout: the all-pairs CSR of the posterior stage (qp_device_result).  Once
+// per run the pairs are ordered by their work (selected third sequences
+// times rows), costliest first.  Per pass: (1) every pair's matrix is
+// transposed into a CSR of the same entry range (rows = residues of the
+// second sequence), so both orientations of every S_ab are rows of some CSR;
+// (2) wavefronts take pairs in that order from a counter, one at a time, and
+// accumulate each block of output rows in LDS -- lanes take (row, z) items,
+// walk row i of S_xz eight entries at a time and, for each entry (k, v), row
+// k of S_zy, adding v * S_zy(k, j) with LDS atomics -- then scale, threshold
+// and compact each row in column order; (3) per-pair counts are scanned and
+// the entries gathered in pair order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
