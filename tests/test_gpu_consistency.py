@@ -161,6 +161,22 @@ def test_relax_more_thirds_than_a_wave(B, params):
     _say("72-sequence relaxation: %d entries, max |d| %.3g" % (res["nnz"], worst))
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_relax_smallest_families(B, params, k):
+    """Two sequences (one pair, no third sequence: h_xy = 1 and the matrix is
+    its own input) and three (each pair has one candidate z), two passes, the
+    tree threshold selecting every z."""
+    import torch
+    thresh, h = 0.01, 3.0
+    fam = W.c1_family()[:k]
+    S0, tdist, arrays = _oracle_stage1(fam, params, thresh)
+    T = int(tdist.max())
+    res = _gpu_relax(B, torch, fam, arrays, tdist, T, h, 2, thresh)
+    S_or = OC.consistency(S0, len(fam), tdist, T, h, 2, thresh)
+    worst = _compare(B, res, fam, S_or, thresh)
+    _say("%d-sequence relaxation: %d entries, max |d| %.3g" % (k, res["nnz"], worst))
+
+
 def test_relax_empty_selection_keeps_input(B, params):
     """T below every tree-guided distance: no relaxation, each matrix is its
     input (h_xy = 1, S' = 2 S / 2)."""
