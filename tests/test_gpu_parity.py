@@ -266,6 +266,25 @@ def test_c2_full_size_sampled(B, params):
     assert np.all((res["dist"] >= -1e-6) & (res["dist"] <= 1.0 + 1e-6))
 
 
+def test_c2_full_size_fp64_sampled(B, params):
+    """The FP64 path on the whole C2 family (19,900 pairs in one launch);
+    50 of the seeded sample pairs against the oracle at the FP64 bar, and
+    every pair's EA distance within 1e-5 of the FP32 path's."""
+    fam = W.c2_family()
+    _say("C2 full size, FP64 path")
+    res = B.qp_posteriors(fam, B.make_params(params, 1), 0.01)
+    assert res["n_pairs"] == 19900
+    sample = W.c2_sample()[::4]
+    orcs = _oracle_pairs(fam, params, [W.pair_of_index(int(p), 200) for p in sample])
+    for p, orc in zip(sample, orcs):
+        i, j = W.pair_of_index(int(p), 200)
+        _check_pair(res, int(p), fam[i], fam[j], orc, 0.01, TOL[1])
+    r32 = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+    d = np.abs(res["dist"] - r32["dist"]).max()
+    _say("C2 FP64 vs FP32 path: max |d EA| %.3g" % d)
+    assert d <= 1e-5
+
+
 def _oracle_pairs(fam, params, ij):
     """Oracle results of the pairs (i, j) in ij, on a thread pool (the C
     oracle runs outside the interpreter lock)."""
