@@ -418,13 +418,14 @@ PER_PAIR = [
 ]
 
 
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("name,lens", PER_PAIR, ids=[e[0] for e in PER_PAIR])
-def test_per_pair_form(B, params, name, lens):
+def test_per_pair_form(B, params, name, lens, prec):
     """The plain per-pair form (one launch of one wave per pair, pair order,
     no graph) gives the batched form's outputs bit for bit, and both meet the
-    oracle bar."""
+    oracle bar, in both precisions."""
     fam = W.c1_family() if lens is None else W.make_family(len(lens), lens, 7, r_sub=0.3, r_indel=0.05)
-    p = B.make_params(params, 0)
+    p = B.make_params(params, prec)
     lens = np.array([len(x) for x in fam], dtype=np.int32)
     off = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
     hip = _hip()
@@ -451,7 +452,7 @@ def test_per_pair_form(B, params, name, lens):
     for i in range(len(fam)):
         for j in range(i + 1, len(fam)):
             orc = oracle.pair(fam[i], fam[j], params, per_model=False)
-            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[prec])
             k += 1
 
 
