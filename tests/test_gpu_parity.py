@@ -457,7 +457,8 @@ def test_per_pair_form(B, params, name, lens, prec):
 
 
 @pytest.mark.parametrize("shift", [1, 2])
-def test_tuned_class_map(B, params, shift):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tuned_class_map(B, params, shift, prec):
     """Pairs run with more rows per lane than their length needs (fewer,
     taller lanes) and on half of each class's persistent grid still meet the
     oracle bar; this is the space the autotuner picks from."""
@@ -466,13 +467,13 @@ def test_tuned_class_map(B, params, shift):
         B.set_tuning([min(8, r + 1 + shift) for r in range(8)], [0.5] * 9)
         for name, fam in (("c1", W.c1_family()),
                           ("mixed", W.make_family(6, [40, 100, 200, 300, 450, 700], 9, r_sub=0.3, r_indel=0.05))):
-            _say("tuned map shift", shift, name)
-            res = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+            _say("tuned map shift", shift, name, "precision", prec)
+            res = B.qp_posteriors(fam, B.make_params(params, prec), 0.01)
             k = 0
             for i in range(len(fam)):
                 for j in range(i + 1, len(fam)):
                     orc = oracle.pair(fam[i], fam[j], params, per_model=False)
-                    _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+                    _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[prec])
                     k += 1
     finally:
         B.set_tuning(before["rows_per_lane"], before["waves_frac"], before["recompute"])
@@ -552,17 +553,19 @@ def test_plan_sized_to_output_bound(B, params):
             k += 1
 
 
-def test_nucleotide_family(B):
-    """Nucleotide mode (alphabet 4) on the device against the oracle."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nucleotide_family(B, prec):
+    """Nucleotide mode (alphabet 4) on the device against the oracle, in both
+    precisions."""
     mp = W.make_nt_params(0)
     fam = W.nt_family(7, [60, 120, 200, 300, 450, 700, 90], 8)
     _say("nucleotide family")
-    res = B.qp_posteriors(fam, B.make_params(mp, 0), 0.01)
+    res = B.qp_posteriors(fam, B.make_params(mp, prec), 0.01)
     k = 0
     for i in range(len(fam)):
         for j in range(i + 1, len(fam)):
             orc = oracle.pair(fam[i], fam[j], mp, per_model=False)
-            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[prec])
             k += 1
 
 
