@@ -94,10 +94,11 @@ def _compare(torch, t, res, P, rows):
     return nnz
 
 
-def test_noalloc_matches_plan_two_calls(B, params):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_noalloc_matches_plan_two_calls(B, params, prec):
     import torch
     from oracle import pair as oracle_pair
-    p = B.make_params(params)
+    p = B.make_params(params, prec)
     thresh = 0.01
     rng = np.random.default_rng(5)
     base = W.c1_family()
@@ -111,7 +112,7 @@ def test_noalloc_matches_plan_two_calls(B, params):
         lens = np.array([len(s) for s in fam], dtype=np.int32)
         t, cap, P, rows = _outputs(torch, lens, thresh, B)
         torch.cuda.synchronize()
-        _say("call %d: %d sequences, %d pairs, capacity %d" % (call + 1, len(fam), P, cap))
+        _say("call %d (precision %d): %d sequences, %d pairs, capacity %d" % (call + 1, prec, len(fam), P, cap))
         keep, took = _run_noalloc(torch, B, fam, p, thresh, t, cap, stream)
         taken.append(took)
         _say("call %d: device memory taken by the call: %d bytes" % (call + 1, took))
