@@ -190,61 +190,65 @@ def test_edge_shapes_fp64(B, params, name, lens):
             k += 1
 
 
-def test_unrelated_and_identical(B, params):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_unrelated_and_identical(B, params, prec):
     rng = np.random.default_rng(11)
     a = rng.integers(0, 20, 150).astype(np.uint8)
     b = rng.integers(0, 20, 170).astype(np.uint8)
     fam = [a, b, a.copy()]
     _say("unrelated / identical")
-    res = B.qp_posteriors(fam, B.make_params(params, 0), 0.01)
+    res = B.qp_posteriors(fam, B.make_params(params, prec), 0.01)
     for k, (i, j) in enumerate([(0, 1), (0, 2), (1, 2)]):
         orc = oracle.pair(fam[i], fam[j], params, per_model=False)
-        _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+        _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[prec])
 
 
-def test_pair_list_and_symmetry(B, params):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pair_list_and_symmetry(B, params, prec):
     """Explicit pairs in both orders: P(y,x) equals P(x,y) transposed."""
     fam = W.c1_family()
     pi = np.array([0, 3, 5, 2], dtype=np.int32)
     pj = np.array([3, 0, 2, 5], dtype=np.int32)
     _say("pair list")
-    res = B.qp_posteriors_pairs(fam, pi, pj, B.make_params(params, 0), 0.01)
+    res = B.qp_posteriors_pairs(fam, pi, pj, B.make_params(params, prec), 0.01)
     assert list(res["pair_i"]) == list(pi) and list(res["pair_j"]) == list(pj)
     for k in range(4):
         orc = oracle.pair(fam[pi[k]], fam[pj[k]], params, per_model=False)
-        _check_pair(res, k, fam[pi[k]], fam[pj[k]], orc, 0.01, TOL[0])
+        _check_pair(res, k, fam[pi[k]], fam[pj[k]], orc, 0.01, TOL[prec])
     d0 = B.pair_dense(res, 0, len(fam[3]))
     d1 = B.pair_dense(res, 1, len(fam[0]))
     assert np.abs(d0 - d1.T).max() <= 2e-5
 
 
-def test_other_models(B, params):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_other_models(B, params, prec):
     """One gap class, a different temperature and HMM weight."""
     fam = W.c1_family()[:3]
     p1 = params.copy(gap_open=(0.03,), gap_extend=(0.6,), temperature=2.0, w_hmm=0.8)
     _say("other models")
-    res = B.qp_posteriors(fam, B.make_params(p1, 0), 0.05)
+    res = B.qp_posteriors(fam, B.make_params(p1, prec), 0.05)
     k = 0
     for i in range(3):
         for j in range(i + 1, 3):
             orc = oracle.pair(fam[i], fam[j], p1, per_model=False)
-            _check_pair(res, k, fam[i], fam[j], orc, 0.05, TOL[0])
+            _check_pair(res, k, fam[i], fam[j], orc, 0.05, TOL[prec])
             k += 1
 
 
 @pytest.mark.parametrize("w", [0.0, 1.0])
-def test_single_model_weight(B, params, w):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_model_weight(B, params, w, prec):
     """w = 1 keeps only the pair-HMM posterior, w = 0 only the partition
     function's; the other model's backward pass then carries zeros."""
     fam = W.c1_family()[:4]
     pw = params.copy(w_hmm=w)
     _say("single model, w =", w)
-    res = B.qp_posteriors(fam, B.make_params(pw, 0), 0.01)
+    res = B.qp_posteriors(fam, B.make_params(pw, prec), 0.01)
     k = 0
     for i in range(4):
         for j in range(i + 1, 4):
             orc = oracle.pair(fam[i], fam[j], pw, per_model=False)
-            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[0])
+            _check_pair(res, k, fam[i], fam[j], orc, 0.01, TOL[prec])
             k += 1
 
 
@@ -397,10 +401,11 @@ def test_device_inputs_unaligned_and_invalid(B, params):
             hip.hipFree(p)
 
 
-def test_deterministic(B, params):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_deterministic(B, params, prec):
     fam = W.c1_family()
     _say("determinism")
-    p = B.make_params(params, 0)
+    p = B.make_params(params, prec)
     a = B.qp_posteriors(fam, p, 0.01)
     b = B.qp_posteriors(fam, p, 0.01)
     for key in ("row_ptr", "col", "val", "dist", "log_z", "nnz_off"):
